@@ -1,0 +1,154 @@
+/*
+ * dpc.h - C ABI of the MI355X exact density-peaks clustering library (libdpc.so).
+ *
+ * The operations are those of Amagata and Hara, "Fast Density-Peaks Clustering:
+ * Multicore-based Parallelization Approach", Section 2.1 (Definitions 1-6):
+ *
+ *   local density     rho_i   = #{ j : dist(p_i, p_j) < d_cut }, p_i itself included (Def. 1, Eq. 1)
+ *   dependent point   q_i     = nearest point of higher density (Def. 2)
+ *   dependent dist.   delta_i = dist(p_i, q_i), +inf for the densest point (Def. 3)
+ *   noise             rho_i < rho_min (Def. 4)
+ *   cluster center    non-noise with delta_i >= delta_min, delta_min > d_cut (Def. 5)
+ *   cluster           non-noise points reachable from a center by dependent links (Def. 6)
+ *
+ * Exact semantics fixed by this library where the paper leaves a choice:
+ *   - points are int32 coordinates in [0, 2^17); distances are compared exactly
+ *     on integer squared distances: dist < d_cut <=> D2 < ceil(d_cut^2);
+ *   - "higher density" is the strict total order (rho descending, id ascending)
+ *     (the paper breaks rho ties arbitrarily / by a random addend, Section 3);
+ *   - among equidistant higher points the smaller id is the dependent point;
+ *   - delta is the correctly rounded FP64 square root of the exact D2;
+ *   - labels are center ids; noise gets -1.
+ *
+ * Conventions for every call:
+ *   - array arguments are DEVICE pointers, allocated and owned by the caller;
+ *     the library never allocates device memory;
+ *   - `ws` is a caller-owned device workspace of at least the size returned by
+ *     the matching *_workspace_bytes call; its contents between calls belong to
+ *     the library (dpc_dependent may reuse the grid left by dpc_density);
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream); calls
+ *     only enqueue work and return without synchronising;
+ *   - errors found on the host are returned at once, with nothing enqueued and
+ *     the outputs untouched; errors found on the device (coordinates out of
+ *     range, inconsistent inputs) are recorded in `ws` and returned by
+ *     dpc_sync_status; every call is memory-safe whatever the input values;
+ *   - calls on distinct workspaces may run concurrently from several threads.
+ */
+#ifndef DPC_H
+#define DPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dpc_status;
+
+#define DPC_OK 0
+#define DPC_EINVAL (-1)     /* bad argument: null pointer, n < 1 or n >= 2^27, d not in [1, 8],
+                               d_cut not finite or <= 0, rho_min < 0, delta_min NaN or <= d_cut */
+#define DPC_ERANGE (-2)     /* a coordinate outside [0, 2^17) (device-detected, see dpc_sync_status);
+                               such coordinates are clamped into range and the results are those of
+                               the clamped points */
+#define DPC_EWORKSPACE (-3) /* ws_bytes smaller than the required workspace */
+#define DPC_EDEVICE (-4)    /* HIP runtime error; dpc_last_error() gives the message */
+
+/* Flag for dpc_dependent: `ws` still holds the grid that dpc_density built for the same
+ * pts, n, d and d_cut, so it is not rebuilt. */
+#define DPC_REUSE_GRID 1u
+
+/* Largest number of points per call (ids must fit 27 bits of a packed (D2, id) key). */
+#define DPC_MAX_POINTS ((int64_t)1 << 27)
+/* Coordinates must lie in [0, DPC_COORD_LIMIT). */
+#define DPC_COORD_LIMIT 131072
+#define DPC_MAX_DIM 8
+
+/* Bytes of workspace needed by dpc_density, dpc_dependent, dpc_label and dpc_run for
+ * these sizes (0 if the arguments are invalid). */
+size_t dpc_workspace_bytes(int64_t n, int32_t d, double d_cut);
+
+/*
+ * Local density (Def. 1, Eq. 1).
+ *   pts  [n][d] int32, row-major, point i at pts + i*d (read only)
+ *   rho  [n] int32 output, rho[i] >= 1
+ */
+dpc_status dpc_density(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32_t *rho,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Dependent point and dependent distance (Defs. 2-3) given the densities `rho`
+ * (normally dpc_density's output).
+ *   dep    [n] int32 output: id of the dependent point, -1 for the densest point
+ *   delta  [n] double output: dist(p_i, p_dep_i), +inf for the densest point
+ *   flags  0 or DPC_REUSE_GRID
+ */
+dpc_status dpc_dependent(const int32_t *pts, int64_t n, int32_t d, double d_cut, const int32_t *rho,
+                         int32_t *dep, double *delta, uint32_t flags, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/*
+ * Noise, centers and cluster labels (Defs. 4-6) from (rho, dep, delta) alone, so
+ * that new thresholds chosen on the decision graph (Section 2.1) only rerun this.
+ *   label     [n] int32 output: id of the point's cluster center, -1 for noise
+ *   ncenters  device int64 output: number of cluster centers
+ * A center's own dependent point is taken to be itself (Section 2.1, after Def. 5).
+ */
+dpc_status dpc_label(int64_t n, const int32_t *rho, const int32_t *dep, const double *delta,
+                     int32_t rho_min, double delta_min, int32_t *label, int64_t *ncenters,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* dpc_density, dpc_dependent (reusing the grid) and dpc_label in one call. */
+dpc_status dpc_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                   double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
+                   int64_t *ncenters, void *ws, size_t ws_bytes, void *stream);
+
+/* Minimum workspace of dpc_label called on its own (the device status header). */
+#define DPC_LABEL_WS_BYTES 256
+
+/* ceil(d_cut^2) as the library computes it (exactly, by an error-free product), clamped to
+ * 2^38 (beyond every squared distance of in-range points); -1 if d_cut is not finite or <= 0.
+ * dist < d_cut <=> D2 < this value for integer squared distances D2 (Def. 1). Host only. */
+int64_t dpc_cutoff_square(double d_cut);
+
+/* The grid a call would use for these sizes, for diagnostics (host only, nothing enqueued). */
+typedef struct {
+  int64_t R;          /* ceil(d_cut^2) */
+  int64_t cell_side;  /* L >= floor(sqrt(R - 1)): the 3^d cells around a point hold its d_cut-ball */
+  int64_t cells_per_dim;
+  int64_t cells;      /* cells_per_dim^d, the dense cell table */
+  int64_t strip_cells;/* cells per strip along the last dimension */
+  int64_t strips;
+  int64_t max_tasks;
+  int64_t mode;       /* 0: packed 16-bit distance path; 1: exact int64 path */
+  int64_t workspace_bytes;
+} dpc_plan_info;
+dpc_status dpc_plan(int64_t n, int32_t d, double d_cut, dpc_plan_info *out);
+
+/* Kernel timing for diagnostics: when enabled, every call records HIP events on its stream
+ * around each kernel group (grid_build, density, rank_keys, rank_sort, ring1, ringk, peaks,
+ * finish, label).  dpc_profile_report waits for them, writes
+ * {"group": [launches, total_ms], ...} as JSON into buf (up to len bytes, NUL-terminated),
+ * returns the full length, and clears the records. */
+void dpc_profile_enable(int32_t on);
+int32_t dpc_profile_report(char *buf, size_t len);
+
+/* Synchronises `stream` and returns the device-detected status of the most recent call on
+ * this workspace: DPC_OK, DPC_ERANGE (coordinates out of range, clamped), DPC_EINVAL (rho or
+ * dep inputs not produced by this library: densities outside [1, n] were clamped, dependent
+ * links that do not rank higher were cut) or DPC_EDEVICE.  Each call starts with a clear
+ * status; this call clears it too. */
+dpc_status dpc_sync_status(void *ws, void *stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *dpc_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int32_t dpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPC_H */

@@ -1,0 +1,246 @@
+// Shared definitions of the HIP library: the launch plan, the workspace layout,
+// the device header and small wave-level helpers.  Internal; the public ABI is
+// include/dpc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/dpc.h"
+
+namespace dpc {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;              // threads per workgroup of the wave-task kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kQueryChunk = 64;          // queries per task: one per lane
+constexpr int64_t kTableMax = int64_t(1) << 26;   // cells of the dense cell table
+constexpr int kIdBits = 27;              // packed key = (D2 << 27) | id
+constexpr uint64_t kIdMask = (uint64_t(1) << kIdBits) - 1;
+constexpr uint64_t kNoKey = ~uint64_t(0);
+constexpr int kScanItems = 16;           // items per thread in the block scan
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kPeakChunk = 8192;         // candidates per peak work unit
+
+enum DistMode : int32_t {
+  kModeP16 = 0,  // low 16 bits of each coordinate, packed two per word; exact while the
+                 // search window keeps |dx| < 2^15 and D2 < 2^31
+  kModeI64 = 1,  // exact int64 squared distances on full coordinates
+};
+
+// Device-side scalars of one workspace.  Counters are reset by the call that uses them.
+struct DevHeader {
+  uint32_t status;        // errors of the current call: bit 0 coordinate out of range, bit 1 inconsistent input
+  uint32_t ntasks;        // tasks of the density / ring-1 kernels (written by the task builder)
+  uint32_t task_next;     // work counter, density kernel
+  uint32_t task_next2;    // work counter, ring-1 kernel
+  uint32_t n_unres;       // points left unresolved by ring-1
+  uint32_t unres_next;    // work counter, ring-k kernel
+  uint32_t n_peaks;       // points left to the rank-prefix scan
+  uint32_t pad0;
+  unsigned long long peak_next;  // work counter, peak kernel ((peak, chunk) units)
+  uint32_t pad[54];
+};
+static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
+
+// Everything a kernel needs to know about one problem and its workspace.
+struct Plan {
+  int64_t n;
+  int32_t d;
+  int32_t words;     // packed 16-bit words per point, (d + 1) / 2
+  int64_t R;         // ceil(d_cut^2)
+  int32_t L;         // cell side
+  int32_t nc;        // cells per dimension
+  int32_t wc;        // strip width in cells along the last dimension
+  int32_t nsx;       // strips per row, ceil(nc / wc)
+  int32_t mode;      // DistMode
+  int32_t pad0;
+  int64_t ncells;    // nc^d
+  int64_t nrows;     // nc^(d-1)
+  int64_t nstrips;   // nrows * nsx
+  int64_t max_tasks;
+  // workspace byte offsets
+  size_t o_hdr, o_cnt, o_bsum, o_key, o_slot, o_spts, o_spk, o_sid, o_sK, o_tcnt, o_tasks, o_rcnt,
+      o_rpts, o_rid, o_best, o_unres, o_peaks, total;
+};
+
+// Pointers into one workspace, resolved from a Plan.
+struct Ws {
+  DevHeader *hdr;
+  uint32_t *cnt;     // [ncells + 1] cell counts, then cell starts (exclusive scan)
+  uint32_t *bsum;    // scan block sums
+  uint32_t *key;     // [n] cell key per id
+  uint32_t *slot;    // [n] slot within the cell (later: slot within the rho bucket)
+  int32_t *spts;     // [n][d] clamped coordinates in cell order
+  uint32_t *spk;     // [n][words] packed low 16 bits of the coordinates, cell order
+  int32_t *sid;      // [n] id at each cell-order position
+  uint64_t *sK;      // [n] (rho << 32) | ~id at each cell-order position
+  uint32_t *tcnt;    // [nstrips + 1] tasks per strip, then task offsets
+  uint4 *tasks;      // [max_tasks] {first query, end query, strip, 0}
+  uint32_t *rcnt;    // [n + 1] rho histogram by (n - rho), then bucket starts
+  int32_t *rpts;     // [n][d] coordinates in rank order
+  int32_t *rid;      // [n] id at each rank position
+  uint64_t *best;    // [n] packed (D2 << 27 | dep) per id, kNoKey if none
+  uint32_t *unres;   // [n + 1] cell-order positions unresolved after ring 1 (+ spare slot)
+  uint32_t *peaks;   // [n + 1] cell-order positions left to the rank-prefix scan (+ spare slot)
+};
+
+inline Ws resolve(const Plan &p, void *base) {
+  char *b = static_cast<char *>(base);
+  Ws w;
+  w.hdr = reinterpret_cast<DevHeader *>(b + p.o_hdr);
+  w.cnt = reinterpret_cast<uint32_t *>(b + p.o_cnt);
+  w.bsum = reinterpret_cast<uint32_t *>(b + p.o_bsum);
+  w.key = reinterpret_cast<uint32_t *>(b + p.o_key);
+  w.slot = reinterpret_cast<uint32_t *>(b + p.o_slot);
+  w.spts = reinterpret_cast<int32_t *>(b + p.o_spts);
+  w.spk = reinterpret_cast<uint32_t *>(b + p.o_spk);
+  w.sid = reinterpret_cast<int32_t *>(b + p.o_sid);
+  w.sK = reinterpret_cast<uint64_t *>(b + p.o_sK);
+  w.tcnt = reinterpret_cast<uint32_t *>(b + p.o_tcnt);
+  w.tasks = reinterpret_cast<uint4 *>(b + p.o_tasks);
+  w.rcnt = reinterpret_cast<uint32_t *>(b + p.o_rcnt);
+  w.rpts = reinterpret_cast<int32_t *>(b + p.o_rpts);
+  w.rid = reinterpret_cast<int32_t *>(b + p.o_rid);
+  w.best = reinterpret_cast<uint64_t *>(b + p.o_best);
+  w.unres = reinterpret_cast<uint32_t *>(b + p.o_unres);
+  w.peaks = reinterpret_cast<uint32_t *>(b + p.o_peaks);
+  return w;
+}
+
+// Host-side launch helpers (implemented in the .hip files).
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_scan(uint32_t *data, int64_t count, uint32_t *bsum, hipStream_t s);
+hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, hipStream_t s);
+hipError_t gather_rank_keys(const Plan &p, const Ws &w, const int32_t *rho, hipStream_t s);
+hipError_t launch_density(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s);
+hipError_t rank_sort(const Plan &p, const Ws &w, hipStream_t s);
+hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, hipStream_t s);
+hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const double *delta,
+                        int32_t rho_min, double delta_min, int32_t *label, int64_t *ncenters,
+                        DevHeader *hdr, hipStream_t s);
+hipError_t reset_counters(DevHeader *hdr, bool grid, hipStream_t s);
+hipError_t clear_status(DevHeader *hdr, hipStream_t s);
+unsigned persistent_blocks(int64_t max_waves);
+
+inline unsigned blocks_for(int64_t items, int per_block) {
+  int64_t b = (items + per_block - 1) / per_block;
+  return static_cast<unsigned>(b < 1 ? 1 : b);
+}
+
+}  // namespace dpc
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+#ifdef __HIP_DEVICE_COMPILE__
+#define DPC_DEVICE_HELPERS 1
+#endif
+
+// Kernel launch on a stream: DPC_LAUNCH((kernel<T...>), grid, block, stream, args...).
+// The kernel name is parenthesised so template argument commas survive the macro.
+#define DPC_STRIP(...) __VA_ARGS__
+#ifndef DPC_LAUNCH
+#define DPC_LAUNCH(K, G, B, S, ...) DPC_STRIP K<<<(G), (B), 0, (S)>>>(__VA_ARGS__)
+#endif
+
+// Read-only global memory seen through the constant address space: uniform loads
+// from it become scalar (SMEM) loads.  Only for data no kernel writes while it runs.
+#ifndef DPC_CONST
+#define DPC_CONST(T) const __attribute__((address_space(4))) T
+#endif
+
+template <typename T>
+__device__ __forceinline__ DPC_CONST(T) * as_const(const T *p) {
+  return (DPC_CONST(T) *)(p);
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (dpc::kWave - 1); }
+
+// 64-bit minimum over the wave.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    uint64_t o = __shfl_xor(v, off, dpc::kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, dpc::kWave);
+  return v;
+}
+
+// Exclusive prefix sum over the wave; *total gets the wave total.
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t *total) {
+  const int lane = lane_id();
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < dpc::kWave; off <<= 1) {
+    uint32_t y = __shfl_up(x, off, dpc::kWave);
+    x += lane >= off ? y : 0u;
+  }
+  *total = __shfl(x, dpc::kWave - 1, dpc::kWave);
+  return x - v;
+}
+
+// Work item / list slot helpers for persistent loops.  They contain no
+// lane-divergent branch: a divergent `if (lane == 0)` around an atomic inside a
+// loop lets the compiler's control-flow structurizer split the loop so that lane
+// 0 falls an iteration behind the others, and the next cross-lane read (a
+// shuffle without lane 0) then never sees a new work item.  Every lane issues the
+// atomic, adding 0 or 1, and the first lane's result is broadcast.
+
+// Slot in a list for each lane with `take` set (distinct, dense from the
+// counter's old value); lanes without `take` get an unspecified value.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool take) {
+  return atomicAdd(counter, take ? 1u : 0u);
+}
+
+// Next work item of the whole wave (all 64 lanes active).
+__device__ __forceinline__ uint32_t wave_next(uint32_t *counter) {
+  const uint32_t t = atomicAdd(counter, lane_id() == 0 ? 1u : 0u);
+  return uniform(t);
+}
+
+// a - b on two packed signed 16-bit halves (wrapping), as a 32-bit word.
+__device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t b) {
+#ifndef DPC_HOST_DOT2
+  typedef short s2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(s2, a) - __builtin_bit_cast(s2, b));
+#else
+  const uint32_t lo = (a - b) & 0xFFFFu, hi = ((a >> 16) - (b >> 16)) & 0xFFFFu;
+  return lo | (hi << 16);
+#endif
+}
+
+// lo*lo + hi*hi + acc on packed signed 16-bit halves (VOP3P v_dot2_i32_i16, acc may be scalar).
+#ifndef DPC_HOST_DOT2
+__device__ __forceinline__ int32_t dot2_self_s(uint32_t a, int32_t acc_uniform) {
+  int32_t r;
+  asm("v_dot2_i32_i16 %0, %1, %1, %2" : "=v"(r) : "v"(a), "s"(acc_uniform));
+  return r;
+}
+__device__ __forceinline__ int32_t dot2_self_v(uint32_t a, int32_t acc) {
+  int32_t r;
+  asm("v_dot2_i32_i16 %0, %1, %1, %2" : "=v"(r) : "v"(a), "v"(acc));
+  return r;
+}
+#else
+__device__ __forceinline__ int32_t dot2_self_v(uint32_t a, int32_t acc) {
+  const int32_t lo = int16_t(a & 0xFFFFu), hi = int16_t(a >> 16);
+  return int32_t(uint32_t(acc) + uint32_t(lo * lo) + uint32_t(hi * hi));
+}
+__device__ __forceinline__ int32_t dot2_self_s(uint32_t a, int32_t acc) { return dot2_self_v(a, acc); }
+#endif

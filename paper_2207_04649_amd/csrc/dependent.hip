@@ -1,0 +1,388 @@
+// Dependent point and dependent distance (Defs. 2-3).
+//
+// q_i is the point with the smallest (D2, id) among the points ranked above i in
+// the order (rho descending, id ascending); delta_i = sqrt(D2).  Ex-DPC finds it
+// with a kd-tree grown in density order (Section 3); here it takes three exact
+// passes, all keyed by the packed u64 (D2 << 27 | id), whose minimum is unique,
+// so every reduction order gives the same answer:
+//
+//  1. ring 1: each task (64 queries) scans its density window; a query whose best
+//     candidate is strictly closer than the window's exterior is final.  Most
+//     points end here, since most dependent distances are below d_cut (Section 3,
+//     after Lemma 2);
+//  2. ring k: one wave per remaining point grows the searched cell block one
+//     shell at a time, skipping cells farther than the best so far, until the
+//     best is strictly closer than the block's exterior, or the remaining work
+//     would exceed a scan of the point's density prefix;
+//  3. peaks: a scan of the density prefix (the points of higher rank, contiguous
+//     in the rank-sorted copy, as in the straightforward algorithm of Section 2.2,
+//     step 3), split over waves and merged with a 64-bit atomic minimum.
+#include "prof.h"
+#include "tasks.h"
+
+namespace dpc {
+namespace {
+
+// -------------------------------------------------------------------- ring 1
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_ring1(Plan p, Ws w) {
+  constexpr int W = (D + 1) / 2;
+  const int lane = lane_id();
+  DPC_CONST(uint32_t) *spk = as_const(w.spk);
+  DPC_CONST(int32_t) *spc = as_const(w.spts);
+  DPC_CONST(uint64_t) *sKc = as_const(w.sK);
+  const uint32_t ntasks = uniform(as_const(&w.hdr->ntasks)[0]);
+
+  for (;;) {
+    const uint32_t t = wave_next(&w.hdr->task_next2);
+    if (t >= ntasks) break;
+    const TaskGeom<D> g = decode_task<D>(p, w.tasks, w.spts, t);
+    const uint32_t q = min(g.qb + uint32_t(lane), g.qe - 1u);
+    const uint64_t Ki = w.sK[q];
+    int32_t qx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) qx[k] = w.spts[int64_t(q) * D + k];
+    uint32_t qk[W];
+    if (MODE == kModeP16) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) qk[k] = w.spk[int64_t(q) * W + k];
+    }
+    // P16: best = (D2 << 32) | id (D2 < 2^31); I64: best = (D2 << 27) | id.
+    uint64_t best = kNoKey;
+    constexpr int NROW = Pow3<D - 1>::value;
+    for (int rb = 0; rb < NROW; rb += kWave) {
+      uint32_t sb = 0, se = 0;
+      if (rb + lane < NROW) window_row<D>(p, g, rb + lane, w.cnt, &sb, &se);
+      const int nr = min(kWave, NROW - rb);
+      for (int r = 0; r < nr; ++r) {
+        const uint32_t b = __builtin_amdgcn_readlane(sb, r);
+        const uint32_t e = __builtin_amdgcn_readlane(se, r);
+        uint32_t j = b;
+        if (MODE == kModeP16) {
+          constexpr int B = 8 / W > 0 ? 8 / W : 1;
+          for (; j + B <= e; j += B) {
+            uint32_t c[B * W];
+            uint64_t kj[B];
+#pragma unroll
+            for (int u = 0; u < B * W; ++u) c[u] = spk[int64_t(j) * W + u];
+#pragma unroll
+            for (int u = 0; u < B; ++u) kj[u] = sKc[j + u];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              int32_t d2 = dot2_self_s(pk_sub16(qk[0], c[u * W]), 0);
+#pragma unroll
+              for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], c[u * W + k]), d2);
+              const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | uint32_t(~uint32_t(kj[u]));
+              best = (kj[u] > Ki && key < best) ? key : best;
+            }
+          }
+          for (; j < e; ++j) {
+            const uint64_t kj = sKc[j];
+            int32_t d2 = dot2_self_s(pk_sub16(qk[0], spk[int64_t(j) * W]), 0);
+#pragma unroll
+            for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], spk[int64_t(j) * W + k]), d2);
+            const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | uint32_t(~uint32_t(kj));
+            best = (kj > Ki && key < best) ? key : best;
+          }
+        } else {
+          for (; j < e; ++j) {
+            const uint64_t kj = sKc[j];
+            int64_t d2 = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+              const int64_t df = int64_t(qx[k] - spc[int64_t(j) * D + k]);
+              d2 += df * df;
+            }
+            const uint64_t key = (uint64_t(d2) << kIdBits) | uint32_t(~uint32_t(kj));
+            best = (kj > Ki && key < best) ? key : best;
+          }
+        }
+      }
+    }
+    if (MODE == kModeP16 && best != kNoKey) best = ((best >> 32) << kIdBits) | (best & 0xFFFFFFFFu);
+    const uint64_t ext = window_exterior_d2<D>(p, g, qx);
+    const bool resolved = ext == kNoKey || (best != kNoKey && (best >> kIdBits) < ext);
+    // Lanes past the end of the task repeat its last query (same values, same
+    // places); only valid lanes append, and the others write the spare slot n.
+    const bool take = g.qb + uint32_t(lane) < g.qe && !resolved;
+    w.best[uint32_t(~uint32_t(Ki))] = best;
+    const uint32_t slot = wave_append(&w.hdr->n_unres, take);
+    w.unres[take ? slot : uint32_t(p.n)] = q;
+  }
+}
+
+// -------------------------------------------------------------------- ring k
+
+struct SegLds {
+  uint32_t off[kWave];  // exclusive prefix of the lanes' candidate counts
+  uint32_t b1[kWave];
+  uint32_t n1[kWave];
+  uint32_t b2[kWave];
+};
+
+__device__ __forceinline__ int64_t gap_to(int32_t x, int64_t lo, int64_t hi) {
+  return x < lo ? lo - x : (x > hi ? x - hi : 0);
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t exact_d2(const int32_t *a, DPC_CONST(int32_t) * b) {
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int64_t df = int64_t(a[k] - b[k]);
+    s += df * df;
+  }
+  return uint64_t(s);
+}
+
+template <int D>
+__device__ __forceinline__ uint64_t exact_d2_v(const int32_t *a, const int32_t *b) {
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int64_t df = int64_t(a[k] - b[k]);
+    s += df * df;
+  }
+  return uint64_t(s);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
+  __shared__ SegLds lds_all[kWavesPerBlock];
+  SegLds &lds = lds_all[threadIdx.x / kWave];
+  const int lane = lane_id();
+  const uint32_t nunres = uniform(as_const(&w.hdr->n_unres)[0]);
+  DPC_CONST(int32_t) *spc = as_const(w.spts);
+  DPC_CONST(uint64_t) *sKc = as_const(w.sK);
+  DPC_CONST(uint32_t) *unres = as_const(w.unres);
+  DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
+
+  for (;;) {
+    const uint32_t u = wave_next(&w.hdr->unres_next);
+    if (u >= nunres) break;
+    const uint32_t q = uniform(unres[u]);
+    int32_t x[D], c[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      x[k] = uniform(spc[int64_t(q) * D + k]);
+      c[k] = x[k] / p.L;
+    }
+    const uint64_t Ki = uniform(sKc[q]);
+    const uint32_t id = uint32_t(~uint32_t(Ki));
+    const int64_t rho = int64_t(Ki >> 32);
+    uint64_t best = uniform(w.best[id]);
+    const uint32_t prefix = uniform(rstart[p.n - rho + 1]);
+    const int64_t budget = int64_t(prefix / kWave) + 2;
+    int64_t cost = 0;
+    bool defer = false;
+
+    for (int k = 2;; ++k) {
+      const int64_t side = 2 * k + 1;
+      int64_t nrows = 1;
+      for (int t = 0; t < D - 1; ++t) nrows *= side;
+      const uint64_t bestd2 = best >> kIdBits;  // huge when there is no best yet
+      for (int64_t rb = 0; rb < nrows; rb += kWave) {
+        uint32_t b1 = 0, n1 = 0, b2 = 0, n2 = 0;
+        const int64_t r0 = rb + lane;
+        if (r0 < nrows) {
+          int64_t r = r0, rowk = 0, md = 0;
+          bool ok = true, full = false;
+#pragma unroll
+          for (int t = 0; t < D - 1; ++t) {
+            const int32_t o = int32_t(r % side) - k;
+            r /= side;
+            const int32_t nb = c[t] + o;
+            ok = ok && nb >= 0 && nb < p.nc;
+            full = full || o == k || o == -k;
+            rowk = rowk * p.nc + nb;
+            const int64_t gp = gap_to(x[t], int64_t(nb) * p.L, int64_t(nb + 1) * p.L - 1);
+            md += gp * gp;
+          }
+          if (ok) {
+            const int32_t cl = c[D - 1];
+            if (full) {
+              const int32_t lo = max(cl - k, 0), hi = min(cl + k, p.nc - 1);
+              const int64_t gp = gap_to(x[D - 1], int64_t(lo) * p.L, int64_t(hi + 1) * p.L - 1);
+              if (uint64_t(md + gp * gp) <= bestd2) {
+                b1 = w.cnt[rowk * p.nc + lo];
+                n1 = w.cnt[rowk * p.nc + hi + 1] - b1;
+              }
+            } else {
+              if (cl - k >= 0) {
+                const int64_t gp = int64_t(x[D - 1]) - (int64_t(cl - k + 1) * p.L - 1);
+                if (uint64_t(md + gp * gp) <= bestd2) {
+                  b1 = w.cnt[rowk * p.nc + cl - k];
+                  n1 = w.cnt[rowk * p.nc + cl - k + 1] - b1;
+                }
+              }
+              if (cl + k < p.nc) {
+                const int64_t gp = int64_t(cl + k) * p.L - int64_t(x[D - 1]);
+                if (uint64_t(md + gp * gp) <= bestd2) {
+                  b2 = w.cnt[rowk * p.nc + cl + k];
+                  n2 = w.cnt[rowk * p.nc + cl + k + 1] - b2;
+                }
+              }
+            }
+          }
+        }
+        uint32_t total;
+        const uint32_t off = wave_exclusive_scan(n1 + n2, &total);
+        total = uniform(total);
+        lds.off[lane] = off;
+        lds.b1[lane] = b1;
+        lds.n1[lane] = n1;
+        lds.b2[lane] = b2;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        uint64_t lbest = kNoKey;
+        for (uint32_t base = 0; base < total; base += kWave) {
+          const uint32_t f = base + uint32_t(lane);
+          if (f < total) {
+            int s = 0;  // last lane whose offset is <= f
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+              if (lds.off[s + step] <= f) s += step;
+            const uint32_t rel = f - lds.off[s];
+            const uint32_t n1s = lds.n1[s];
+            const uint32_t pos = rel < n1s ? lds.b1[s] + rel : lds.b2[s] + (rel - n1s);
+            const uint64_t kj = w.sK[pos];
+            if (kj > Ki) {
+              int32_t y[D];
+#pragma unroll
+              for (int t = 0; t < D; ++t) y[t] = w.spts[int64_t(pos) * D + t];
+              const uint64_t key = (exact_d2_v<D>(x, y) << kIdBits) | uint32_t(~uint32_t(kj));
+              lbest = key < lbest ? key : lbest;
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t wb = uniform(wave_min_u64(lbest));
+        best = wb < best ? wb : best;
+        cost += 1 + (total + kWave - 1) / kWave;
+        if (cost >= budget) break;  // high d: a shell can hold many row batches
+      }
+      if (cost >= budget) {  // shell k may be incomplete: only the prefix scan is exact now
+        defer = true;
+        break;
+      }
+      // The searched block is now every cell within k of the point's cell.
+      int64_t gap = INT64_MAX;
+#pragma unroll
+      for (int t = 0; t < D; ++t) {
+        if (c[t] - k >= 1) gap = min(gap, int64_t(x[t]) - int64_t(c[t] - k) * p.L + 1);
+        if (c[t] + k <= p.nc - 2) gap = min(gap, int64_t(c[t] + k + 1) * p.L - int64_t(x[t]));
+      }
+      if (gap == INT64_MAX) break;  // the block covers the whole grid
+      if (best != kNoKey && (best >> kIdBits) < uint64_t(gap) * uint64_t(gap)) break;
+    }
+    // Every lane stores the same values (no lane-divergent branch in the loop).
+    w.best[id] = best;
+    const uint32_t slot = uniform(wave_append(&w.hdr->n_peaks, defer && lane == 0));
+    w.peaks[defer ? slot : uint32_t(p.n)] = q;
+  }
+}
+
+// -------------------------------------------------------------------- peaks
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
+  const int lane = lane_id();
+  const uint64_t npeaks = uniform(as_const(&w.hdr->n_peaks)[0]);
+  const uint64_t cpp = uint64_t((p.n + kPeakChunk - 1) / kPeakChunk);
+  const uint64_t units = npeaks * cpp;
+  DPC_CONST(int32_t) *spc = as_const(w.spts);
+  DPC_CONST(uint64_t) *sKc = as_const(w.sK);
+  DPC_CONST(uint32_t) *peaks = as_const(w.peaks);
+  DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
+
+  for (;;) {
+    const uint64_t u = uniform(static_cast<uint64_t>(atomicAdd(&w.hdr->peak_next, lane == 0 ? 1ull : 0ull)));
+    if (u >= units) break;
+    const uint32_t pk = uint32_t(u / cpp);
+    const uint64_t ch = u % cpp;
+    const uint32_t q = uniform(peaks[pk]);
+    const uint64_t Ki = uniform(sKc[q]);
+    const uint32_t id = uint32_t(~uint32_t(Ki));
+    const int64_t rho = int64_t(Ki >> 32);
+    const uint32_t bstart = uniform(rstart[p.n - rho]);
+    const uint32_t bend = uniform(rstart[p.n - rho + 1]);
+    const uint64_t r0 = ch * kPeakChunk;
+    const uint64_t r1 = min(r0 + kPeakChunk, uint64_t(bend));
+    int32_t x[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) x[t] = uniform(spc[int64_t(q) * D + t]);
+    uint64_t lbest = kNoKey;
+    for (uint64_t r = r0 + lane; r < r1; r += kWave) {
+      const uint32_t j = uint32_t(w.rid[r]);
+      if (r < bstart || j < id) {
+        int32_t y[D];
+#pragma unroll
+        for (int t = 0; t < D; ++t) y[t] = w.rpts[r * D + t];
+        const uint64_t key = (exact_d2_v<D>(x, y) << kIdBits) | j;
+        lbest = key < lbest ? key : lbest;
+      }
+    }
+    // All lanes merge the same wave minimum (kNoKey leaves the entry unchanged).
+    const uint64_t wb = wave_min_u64(lbest);
+    atomicMin(reinterpret_cast<unsigned long long *>(&w.best[id]), static_cast<unsigned long long>(wb));
+  }
+}
+
+// -------------------------------------------------------------------- finish
+
+__global__ void k_finish(Plan p, const uint64_t *__restrict__ best, int32_t *__restrict__ dep,
+                         double *__restrict__ delta) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const uint64_t key = best[i];
+  if (key == kNoKey) {
+    dep[i] = -1;
+    delta[i] = __builtin_huge_val();
+  } else {
+    dep[i] = int32_t(key & kIdMask);
+    delta[i] = __builtin_sqrt(double(key >> kIdBits));  // correctly rounded (IEEE sqrt)
+  }
+}
+
+template <int D>
+hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta, hipStream_t s) {
+  const unsigned tb = persistent_blocks(p.max_tasks);
+  {
+    ProfScope ps(s, kProfRing1);
+    if (p.mode == kModeP16)
+      DPC_LAUNCH((k_ring1<D, kModeP16>), tb, kBlock, s, p, w);
+    else
+      DPC_LAUNCH((k_ring1<D, kModeI64>), tb, kBlock, s, p, w);
+  }
+  const unsigned rb = persistent_blocks(p.n);
+  {
+    ProfScope ps(s, kProfRingK);
+    DPC_LAUNCH((k_ringk<D>), rb, kBlock, s, p, w);
+  }
+  {
+    ProfScope ps(s, kProfPeaks);
+    DPC_LAUNCH((k_peaks<D>), rb, kBlock, s, p, w);
+  }
+  ProfScope ps(s, kProfFinish);
+  DPC_LAUNCH((k_finish), blocks_for(p.n, kBlock), kBlock, s, p, w.best, dep, delta);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, hipStream_t s) {
+  switch (p.d) {
+    case 1: return launch_dep_d<1>(p, w, dep, delta, s);
+    case 2: return launch_dep_d<2>(p, w, dep, delta, s);
+    case 3: return launch_dep_d<3>(p, w, dep, delta, s);
+    case 4: return launch_dep_d<4>(p, w, dep, delta, s);
+    case 5: return launch_dep_d<5>(p, w, dep, delta, s);
+    case 6: return launch_dep_d<6>(p, w, dep, delta, s);
+    case 7: return launch_dep_d<7>(p, w, dep, delta, s);
+    case 8: return launch_dep_d<8>(p, w, dep, delta, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dpc

@@ -1,0 +1,185 @@
+"""Python binding of libdpc.so (include/dpc.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls.  Tensors are
+torch device tensors (torch provides device memory and streams); every step of
+the computation runs in the library's HIP kernels.  There is no fallback: if
+the library is not built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpc.so")
+
+DPC_OK, DPC_EINVAL, DPC_ERANGE, DPC_EWORKSPACE, DPC_EDEVICE = 0, -1, -2, -3, -4
+DPC_REUSE_GRID = 1
+DPC_LABEL_WS_BYTES = 256
+COORD_LIMIT = 131072
+MAX_POINTS = 1 << 27
+
+_lib = None
+
+
+class DpcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"dpc status {status}: {message}")
+        self.status = status
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "R", "cell_side", "cells_per_dim", "cells", "strip_cells", "strips", "max_tasks", "mode",
+        "workspace_bytes")]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libdpc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_2207_04649_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, U32, D, SZ = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                   ctypes.c_double, ctypes.c_size_t)
+        sig = {
+            "dpc_workspace_bytes": (SZ, [I64, I32, D]),
+            "dpc_density": (I32, [P, I64, I32, D, P, P, SZ, P]),
+            "dpc_dependent": (I32, [P, I64, I32, D, P, P, P, U32, P, SZ, P]),
+            "dpc_label": (I32, [I64, P, P, P, I32, D, P, P, P, SZ, P]),
+            "dpc_run": (I32, [P, I64, I32, D, I32, D, P, P, P, P, P, P, SZ, P]),
+            "dpc_sync_status": (I32, [P, P]),
+            "dpc_last_error": (ctypes.c_char_p, []),
+            "dpc_version": (I32, []),
+            "dpc_cutoff_square": (I64, [D]),
+            "dpc_plan": (I32, [I64, I32, D, ctypes.POINTER(PlanInfo)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != DPC_OK:
+        raise DpcError(status, lib().dpc_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t: torch.Tensor | None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype: torch.dtype, shape: tuple, name: str) -> None:
+    if t.dtype != dtype or tuple(t.shape) != shape or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {shape}")
+
+
+def dpc_version() -> int:
+    return int(lib().dpc_version())
+
+
+def dpc_cutoff_square(d_cut: float) -> int:
+    return int(lib().dpc_cutoff_square(float(d_cut)))
+
+
+def dpc_plan(n: int, d: int, d_cut: float) -> dict:
+    info = PlanInfo()
+    _check(lib().dpc_plan(int(n), int(d), float(d_cut), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def dpc_workspace_bytes(n: int, d: int, d_cut: float) -> int:
+    return int(lib().dpc_workspace_bytes(int(n), int(d), float(d_cut)))
+
+
+def workspace(n: int, d: int, d_cut: float, device="cuda") -> torch.Tensor:
+    nbytes = dpc_workspace_bytes(n, d, d_cut)
+    if nbytes == 0:
+        raise DpcError(DPC_EINVAL, "no workspace for these sizes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _pts(pts: torch.Tensor) -> tuple[int, int]:
+    if pts.dim() != 2:
+        raise ValueError("pts must be [n, d]")
+    n, d = int(pts.shape[0]), int(pts.shape[1])
+    _need(pts, torch.int32, (n, d), "pts")
+    return n, d
+
+
+def dpc_density(pts: torch.Tensor, d_cut: float, rho: torch.Tensor | None = None,
+                ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    n, d = _pts(pts)
+    rho = torch.empty(n, dtype=torch.int32, device=pts.device) if rho is None else rho
+    _need(rho, torch.int32, (n,), "rho")
+    ws = workspace(n, d, d_cut, pts.device) if ws is None else ws
+    _check(lib().dpc_density(_ptr(pts), n, d, float(d_cut), _ptr(rho), _ptr(ws), ws.numel(), _stream(stream)))
+    return rho
+
+
+def dpc_dependent(pts: torch.Tensor, d_cut: float, rho: torch.Tensor, dep: torch.Tensor | None = None,
+                  delta: torch.Tensor | None = None, flags: int = 0, ws: torch.Tensor | None = None,
+                  stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+    n, d = _pts(pts)
+    _need(rho, torch.int32, (n,), "rho")
+    dep = torch.empty(n, dtype=torch.int32, device=pts.device) if dep is None else dep
+    delta = torch.empty(n, dtype=torch.float64, device=pts.device) if delta is None else delta
+    _need(dep, torch.int32, (n,), "dep")
+    _need(delta, torch.float64, (n,), "delta")
+    ws = workspace(n, d, d_cut, pts.device) if ws is None else ws
+    _check(lib().dpc_dependent(_ptr(pts), n, d, float(d_cut), _ptr(rho), _ptr(dep), _ptr(delta), int(flags),
+                               _ptr(ws), ws.numel(), _stream(stream)))
+    return dep, delta
+
+
+def dpc_label(rho: torch.Tensor, dep: torch.Tensor, delta: torch.Tensor, rho_min: int, delta_min: float,
+              label: torch.Tensor | None = None, ncenters: torch.Tensor | None = None,
+              ws: torch.Tensor | None = None, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+    n = int(rho.shape[0])
+    _need(rho, torch.int32, (n,), "rho")
+    _need(dep, torch.int32, (n,), "dep")
+    _need(delta, torch.float64, (n,), "delta")
+    label = torch.empty(n, dtype=torch.int32, device=rho.device) if label is None else label
+    ncenters = torch.empty(1, dtype=torch.int64, device=rho.device) if ncenters is None else ncenters
+    _need(label, torch.int32, (n,), "label")
+    _need(ncenters, torch.int64, (1,), "ncenters")
+    ws = torch.empty(DPC_LABEL_WS_BYTES, dtype=torch.uint8, device=rho.device) if ws is None else ws
+    _check(lib().dpc_label(n, _ptr(rho), _ptr(dep), _ptr(delta), int(rho_min), float(delta_min), _ptr(label),
+                           _ptr(ncenters), _ptr(ws), ws.numel(), _stream(stream)))
+    return label, ncenters
+
+
+def dpc_run(pts: torch.Tensor, d_cut: float, rho_min: int, delta_min: float, ws: torch.Tensor | None = None,
+            out: dict | None = None, stream=None) -> dict:
+    """rho, dep, delta, label and ncenters in one call (device tensors)."""
+    n, d = _pts(pts)
+    dev = pts.device
+    out = out if out is not None else {}
+    rho = out.setdefault("rho", torch.empty(n, dtype=torch.int32, device=dev))
+    dep = out.setdefault("dep", torch.empty(n, dtype=torch.int32, device=dev))
+    delta = out.setdefault("delta", torch.empty(n, dtype=torch.float64, device=dev))
+    label = out.setdefault("label", torch.empty(n, dtype=torch.int32, device=dev))
+    ncent = out.setdefault("ncenters", torch.empty(1, dtype=torch.int64, device=dev))
+    ws = workspace(n, d, d_cut, dev) if ws is None else ws
+    _check(lib().dpc_run(_ptr(pts), n, d, float(d_cut), int(rho_min), float(delta_min), _ptr(rho), _ptr(dep),
+                         _ptr(delta), _ptr(label), _ptr(ncent), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def dpc_sync_status(ws: torch.Tensor, stream=None) -> None:
+    """Synchronise and raise DpcError if the device flagged an error on this workspace."""
+    _check(lib().dpc_sync_status(_ptr(ws), _stream(stream)))

@@ -1,0 +1,22 @@
+"""Build the library's kernel sources as a CPU program (see hip/hip_runtime.h here)."""
+from __future__ import annotations
+
+import glob
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2207_04649_amd", "csrc")
+
+
+def build(out_dir: str, asan: bool = False) -> str:
+    os.makedirs(out_dir, exist_ok=True)
+    exe = os.path.join(out_dir, "dpc_emu_asan" if asan else "dpc_emu")
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-x", "c++", "-I", HERE, "-I", os.path.join(ROOT, "include"), *srcs,
+           "-x", "none", os.path.join(HERE, "driver.cpp"), "-o", exe]
+    if asan:
+        cmd[1:1] = ["-fsanitize=address", "-fno-omit-frame-pointer"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return exe

@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU): exported symbols, the exact cut-off,
+grid plans and argument validation.  Nothing here launches a kernel."""
+import ctypes
+import math
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import dpc_oracle
+from paper_2207_04649_amd import dpc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for f in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if f.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(dpc_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(dpc.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_cutoff_square_matches_oracle():
+    rng = np.random.default_rng(0)
+    vals = [0.5, 1.0, 2.8, 3.0, math.sqrt(2.0), 1000.0, 199.99999999999997, 1e-300, 5e-324]
+    vals += list(rng.uniform(0, 3000, 2000)) + list(np.exp(rng.uniform(-10, 13, 2000)))
+    vals += [math.nextafter(float(v), math.inf) for v in range(1, 400)]
+    vals += [math.nextafter(float(v), 0.0) for v in range(1, 400)]
+    vals += [math.sqrt(float(k)) for k in range(1, 3000)]
+    for v in vals:
+        want = dpc_oracle.cutoff_square(float(v))
+        want = min(want, 1 << 38)
+        assert dpc.dpc_cutoff_square(v) == want, v
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        assert dpc.dpc_cutoff_square(bad) == -1
+
+
+@pytest.mark.parametrize("n,d,d_cut", [(1, 1, 0.5), (20000, 2, 1000.0), (1_000_000, 2, 200.0),
+                                       (4_000_000, 4, 1500.0), (5000, 3, 77.7), (50000, 6, 3000.0),
+                                       (50000, 8, 3000.0), (100, 2, 50000.0), (10, 5, 1e6)])
+def test_plan_invariants(n, d, d_cut):
+    p = dpc.dpc_plan(n, d, d_cut)
+    R = min(math.ceil(Fraction(d_cut) ** 2), 1 << 38)
+    assert p["R"] == R
+    L = p["cell_side"]
+    assert L >= max(1, math.isqrt(R - 1)), "3^d cells must hold the d_cut-ball"
+    assert p["cells_per_dim"] * L >= dpc.COORD_LIMIT
+    assert p["cells"] == p["cells_per_dim"] ** d <= 1 << 26
+    if p["mode"] == 0:  # packed 16-bit path: window extent keeps |dx| < 2^15 and D2 < 2^31
+        E = (p["strip_cells"] + 2) * L
+        assert E - 1 <= 32767 and d * (E - 1) ** 2 <= 2 ** 31 - 1
+    assert p["workspace_bytes"] == dpc.dpc_workspace_bytes(n, d, d_cut) > 0
+
+
+def test_argument_validation_enqueues_nothing():
+    L = dpc.lib()
+    P = ctypes.c_void_p
+    fake = P(4096)
+    assert L.dpc_density(P(0), 10, 2, 1.0, fake, fake, 1 << 30, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_density(fake, 0, 2, 1.0, fake, fake, 1 << 30, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_density(fake, 1 << 27, 2, 1.0, fake, fake, 1 << 40, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_density(fake, 10, 0, 1.0, fake, fake, 1 << 30, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_density(fake, 10, 9, 1.0, fake, fake, 1 << 30, P(0)) == dpc.DPC_EINVAL
+    for bad in (0.0, -2.0, float("nan"), float("inf")):
+        assert L.dpc_density(fake, 10, 2, bad, fake, fake, 1 << 30, P(0)) == dpc.DPC_EINVAL
+    need = dpc.dpc_workspace_bytes(10, 2, 1.0)
+    assert L.dpc_density(fake, 10, 2, 1.0, fake, fake, need - 1, P(0)) == dpc.DPC_EWORKSPACE
+    assert b"workspace" in L.dpc_last_error()
+    assert L.dpc_dependent(fake, 10, 2, 1.0, fake, fake, fake, 2, fake, need, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_label(10, fake, fake, fake, -1, 5.0, fake, fake, fake, 256, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_label(10, fake, fake, fake, 1, float("nan"), fake, fake, fake, 256, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_label(10, fake, fake, fake, 1, 5.0, fake, fake, fake, 255, P(0)) == dpc.DPC_EWORKSPACE
+    # Def. 5 requires delta_min > d_cut.
+    assert L.dpc_run(fake, 10, 2, 3.0, 1, 3.0, fake, fake, fake, fake, fake, fake, need, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_workspace_bytes(0, 2, 1.0) == 0

@@ -1,0 +1,82 @@
+"""The library's kernel sources run on the CPU (no GPU): every GPU thread is a
+fiber and wave intrinsics are lockstep rendezvous (tests/cpu_emu).  This checks
+the kernels' logic, termination and memory bounds (AddressSanitizer) against the
+oracle before anything runs on a GPU.  It does not model the GPU's compiler or
+memory system."""
+import os
+import struct
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import scan
+from paper_2207_04649_amd import inputs
+from tests import oracle_pins as pins
+from tests.cpu_emu import build_emu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def emu_exe():
+    return build_emu.build(os.path.join(ROOT, "_build", "emu"), asan=True)
+
+
+def run_emu(exe, pts, d_cut, rho_min, delta_min):
+    pts = np.ascontiguousarray(pts, np.int32)
+    n, d = pts.shape
+    with tempfile.TemporaryDirectory() as tmp:
+        fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
+        with open(fin, "wb") as f:
+            f.write(struct.pack("<qidid", n, d, float(d_cut), int(rho_min), float(delta_min)))
+            f.write(pts.tobytes())
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:detect_stack_use_after_return=0")
+        r = subprocess.run([exe, fin, fout], capture_output=True, text=True, timeout=600, env=env)
+        assert r.returncode == 0, r.stderr[-3000:]
+        b = open(fout, "rb").read()
+    st, st2, nc = struct.unpack("<iiq", b[:16])
+    o = 16
+    out = {"status": st, "sync": st2, "ncenters": nc}
+    for k, dt, sz in (("rho", np.int32, 4), ("dep", np.int32, 4), ("delta", np.float64, 8), ("label", np.int32, 4)):
+        out[k] = np.frombuffer(b, dt, n, o).copy()
+        o += sz * n
+    return out
+
+
+# The dense cell table spans the whole coordinate domain, so the cut-offs here keep
+# it small enough for an emulated fill and scan (both the 16-bit and int64 paths run).
+CASES = [(seed, d, n, dc) for seed in range(2)
+         for d, dc, ns in [(1, 40.0, (3, 900)), (2, 300.0, (1, 200, 900)), (2, 3000.0, (200,)),
+                           (3, 2000.0, (200,)), (4, 4500.0, (150,)), (6, 14000.0, (40,)), (8, 27000.0, (12,))]
+         for n in ns]
+
+
+@pytest.mark.parametrize("seed,d,n,d_cut", CASES)
+def test_emulated_kernels_match_oracle(emu_exe, seed, d, n, d_cut):
+    pts = inputs.uniform_points(n, d, 131071, 31 * seed + 7 * d + n)
+    if seed == 1:  # clustered copies: duplicates and many equal densities
+        pts[n // 2:] = pts[: n - n // 2] + (pts[: n - n // 2] % 3)
+        pts = np.clip(pts, 0, 131071).astype(np.int32)
+    got = run_emu(emu_exe, pts, d_cut, 2, d_cut * 1.7)
+    assert got["status"] == 0 and got["sync"] == 0
+    pins.assert_same(got, pins.run(scan, pts, d_cut, 2, d_cut * 1.7), keys=("rho", "dep", "delta", "label", "ncenters"),
+                     ctx=f"seed={seed} d={d} n={n}")
+
+
+def test_emulated_blob_job(emu_exe):
+    job = inputs.blob_job(12345, 2500, 2, 6, 500.0, 2000.0, 0.05)
+    got = run_emu(emu_exe, job.pts, job.d_cut, job.rho_min, job.delta_min)
+    pins.assert_same(got, pins.run(scan, job.pts, job.d_cut, job.rho_min, job.delta_min),
+                     keys=("rho", "dep", "delta", "label", "ncenters"), ctx="blob job")
+
+
+def test_emulated_out_of_range_is_flagged_and_bounded(emu_exe):
+    pts = inputs.uniform_points(300, 3, 131071, 4)
+    pts[5, 1] = -17
+    pts[9, 2] = 131072 + 5000
+    got = run_emu(emu_exe, pts, 2500.0, 1, 4000.0)
+    assert got["status"] == 0 and got["sync"] == -2
+    pins.assert_same(got, pins.run(scan, np.clip(pts, 0, 131071), 2500.0, 1, 4000.0),
+                     keys=("rho", "dep", "delta", "label"), ctx="clamped")
