@@ -21,7 +21,9 @@ constexpr uint64_t kIdMask = (uint64_t(1) << kIdBits) - 1;
 constexpr uint64_t kNoKey = ~uint64_t(0);
 constexpr int kScanItems = 16;           // items per thread in the block scan
 constexpr int kScanTile = kBlock * kScanItems;
-constexpr int kPeakChunk = 8192;         // candidates per peak work unit
+constexpr int kPeakChunk = 8192;         // least candidates per peak work unit
+constexpr int kPeakSplit = 16;           // most work units per peak
+constexpr int kRingCostCap = 48;         // most ring-search steps per point before the prefix scan
 
 enum DistMode : int32_t {
   kModeP16 = 0,  // low 16 bits of each coordinate, packed two per word; exact while the
@@ -207,6 +209,15 @@ __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t *to
 __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool take) {
   return atomicAdd(counter, take ? 1u : 0u);
 }
+
+// Index of the calling wave in the grid, and the number of waves: persistent
+// kernels take items wave_index(), wave_index() + grid_waves(), ...  A static
+// interleave needs no shared counter; one returning atomic per work item on a
+// single address serialises in L2 and delays the whole grid.
+__device__ __forceinline__ uint32_t wave_index() {
+  return uniform(uint32_t(blockIdx.x * dpc::kWavesPerBlock + threadIdx.x / dpc::kWave));
+}
+__device__ __forceinline__ uint32_t grid_waves() { return uint32_t(gridDim.x * dpc::kWavesPerBlock); }
 
 // Next work item of the whole wave (all 64 lanes active).
 __device__ __forceinline__ uint32_t wave_next(uint32_t *counter) {

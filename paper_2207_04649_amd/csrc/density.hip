@@ -6,7 +6,7 @@
 // scalar operand; no LDS, no barriers.  Tasks are handed out by a global work
 // counter, so the cost spread between dense and sparse cells balances
 // dynamically (the paper's dynamic per-point scheduling, Section 3, in
-// wave-sized units).
+// wave-sized units).  Waves take tasks in a static interleave (see wave_index).
 #include "tasks.h"
 
 namespace dpc {
@@ -22,9 +22,8 @@ __global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w, int32_t *__res
   const uint32_t ntasks = uniform(as_const(&w.hdr->ntasks)[0]);
   const int32_t negR = -int32_t(p.R < INT32_MAX ? p.R : INT32_MAX);
 
-  for (;;) {
-    const uint32_t t = wave_next(&w.hdr->task_next);
-    if (t >= ntasks) break;
+  const uint32_t nw = grid_waves();
+  for (uint32_t t = wave_index(); t < ntasks; t += nw) {
     const TaskGeom<D> g = decode_task<D>(p, w.tasks, w.spts, t);
     const uint32_t q = min(g.qb + uint32_t(lane), g.qe - 1u);
     uint32_t qk[W];

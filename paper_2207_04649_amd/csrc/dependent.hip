@@ -34,9 +34,8 @@ __global__ __launch_bounds__(kBlock) void k_ring1(Plan p, Ws w) {
   DPC_CONST(uint64_t) *sKc = as_const(w.sK);
   const uint32_t ntasks = uniform(as_const(&w.hdr->ntasks)[0]);
 
-  for (;;) {
-    const uint32_t t = wave_next(&w.hdr->task_next2);
-    if (t >= ntasks) break;
+  const uint32_t nw = grid_waves();
+  for (uint32_t t = wave_index(); t < ntasks; t += nw) {
     const TaskGeom<D> g = decode_task<D>(p, w.tasks, w.spts, t);
     const uint32_t q = min(g.qb + uint32_t(lane), g.qe - 1u);
     const uint64_t Ki = w.sK[q];
@@ -147,6 +146,22 @@ __device__ __forceinline__ uint64_t exact_d2_v(const int32_t *a, const int32_t *
   return uint64_t(s);
 }
 
+// Largest r with r * r <= v (v < 2^38).
+__device__ __forceinline__ int64_t isqrt_floor(uint64_t v) {
+  int64_t r = int64_t(__builtin_sqrt(double(v)));
+  while (r > 0 && uint64_t(r) * uint64_t(r) > v) --r;
+  while (uint64_t(r + 1) * uint64_t(r + 1) <= v) ++r;
+  return r;
+}
+
+// Ring search for the points ring 1 left open.  The searched block grows from
+// the cells within k0 = 1 of the point's cell to k1 = 2 k0 (an annulus per
+// pass, so a sparse neighbourhood needs a logarithmic number of passes).  In
+// every row of the annulus the cell range is clipped to the cells that can
+// still hold a point within the best distance so far, and a row farther than
+// that is skipped.  The point is final once its best candidate is strictly
+// closer than the exterior of the block; it goes to the prefix scan when the
+// passes have cost more than that scan would.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
   __shared__ SegLds lds_all[kWavesPerBlock];
@@ -158,9 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
   DPC_CONST(uint32_t) *unres = as_const(w.unres);
   DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
 
-  for (;;) {
-    const uint32_t u = wave_next(&w.hdr->unres_next);
-    if (u >= nunres) break;
+  const uint32_t nw = grid_waves();
+  for (uint32_t u = wave_index(); u < nunres; u += nw) {
     const uint32_t q = uniform(unres[u]);
     int32_t x[D], c[D];
 #pragma unroll
@@ -173,12 +187,14 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
     const int64_t rho = int64_t(Ki >> 32);
     uint64_t best = uniform(w.best[id]);
     const uint32_t prefix = uniform(rstart[p.n - rho + 1]);
-    const int64_t budget = int64_t(prefix / kWave) + 2;
+    const int64_t budget = min(int64_t(prefix / kWave) + 2, int64_t(kRingCostCap));
     int64_t cost = 0;
     bool defer = false;
+    int32_t k0 = 1;
 
-    for (int k = 2;; ++k) {
-      const int64_t side = 2 * k + 1;
+    for (;;) {
+      const int32_t k1 = 2 * k0;
+      const int64_t side = 2 * int64_t(k1) + 1;
       int64_t nrows = 1;
       for (int t = 0; t < D - 1; ++t) nrows *= side;
       const uint64_t bestd2 = best >> kIdBits;  // huge when there is no best yet
@@ -187,41 +203,42 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
         const int64_t r0 = rb + lane;
         if (r0 < nrows) {
           int64_t r = r0, rowk = 0, md = 0;
-          bool ok = true, full = false;
+          bool ok = true, outer = false;
 #pragma unroll
           for (int t = 0; t < D - 1; ++t) {
-            const int32_t o = int32_t(r % side) - k;
+            const int32_t o = int32_t(r % side) - k1;
             r /= side;
             const int32_t nb = c[t] + o;
             ok = ok && nb >= 0 && nb < p.nc;
-            full = full || o == k || o == -k;
+            outer = outer || o > k0 || o < -k0;
             rowk = rowk * p.nc + nb;
             const int64_t gp = gap_to(x[t], int64_t(nb) * p.L, int64_t(nb + 1) * p.L - 1);
             md += gp * gp;
           }
-          if (ok) {
+          if (ok && uint64_t(md) <= bestd2) {
+            // last-dimension cells that can hold a point within the best distance
             const int32_t cl = c[D - 1];
-            if (full) {
-              const int32_t lo = max(cl - k, 0), hi = min(cl + k, p.nc - 1);
-              const int64_t gp = gap_to(x[D - 1], int64_t(lo) * p.L, int64_t(hi + 1) * p.L - 1);
-              if (uint64_t(md + gp * gp) <= bestd2) {
-                b1 = w.cnt[rowk * p.nc + lo];
-                n1 = w.cnt[rowk * p.nc + hi + 1] - b1;
+            int32_t lo = max(cl - k1, 0), hi = min(cl + k1, p.nc - 1);
+            if (bestd2 < (uint64_t(1) << 38)) {
+              const int64_t rr = isqrt_floor(bestd2 - uint64_t(md));
+              lo = max(lo, int32_t(max(int64_t(x[D - 1]) - rr, int64_t(0)) / p.L));
+              hi = min(hi, int32_t(min(int64_t(x[D - 1]) + rr, int64_t(DPC_COORD_LIMIT - 1)) / p.L));
+            }
+            const int64_t base = rowk * p.nc;
+            if (outer) {  // the whole row lies outside the block searched so far
+              if (lo <= hi) {
+                b1 = w.cnt[base + lo];
+                n1 = w.cnt[base + hi + 1] - b1;
               }
-            } else {
-              if (cl - k >= 0) {
-                const int64_t gp = int64_t(x[D - 1]) - (int64_t(cl - k + 1) * p.L - 1);
-                if (uint64_t(md + gp * gp) <= bestd2) {
-                  b1 = w.cnt[rowk * p.nc + cl - k];
-                  n1 = w.cnt[rowk * p.nc + cl - k + 1] - b1;
-                }
+            } else {  // two pieces: left and right of the searched block
+              const int32_t l_hi = min(hi, cl - k0 - 1), r_lo = max(lo, cl + k0 + 1);
+              if (lo <= l_hi) {
+                b1 = w.cnt[base + lo];
+                n1 = w.cnt[base + l_hi + 1] - b1;
               }
-              if (cl + k < p.nc) {
-                const int64_t gp = int64_t(cl + k) * p.L - int64_t(x[D - 1]);
-                if (uint64_t(md + gp * gp) <= bestd2) {
-                  b2 = w.cnt[rowk * p.nc + cl + k];
-                  n2 = w.cnt[rowk * p.nc + cl + k + 1] - b2;
-                }
+              if (r_lo <= hi) {
+                b2 = w.cnt[base + r_lo];
+                n2 = w.cnt[base + hi + 1] - b2;
               }
             }
           }
@@ -229,6 +246,10 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
         uint32_t total;
         const uint32_t off = wave_exclusive_scan(n1 + n2, &total);
         total = uniform(total);
+        cost += 1 + (total + kWave - 1) / kWave;
+        // Stop before a batch that would cost more than scanning the density
+        // prefix (a dense neighbourhood around a density peak).
+        if (cost >= budget) break;
         lds.off[lane] = off;
         lds.b1[lane] = b1;
         lds.n1[lane] = n1;
@@ -236,8 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         uint64_t lbest = kNoKey;
-        for (uint32_t base = 0; base < total; base += kWave) {
-          const uint32_t f = base + uint32_t(lane);
+        for (uint32_t fb = 0; fb < total; fb += kWave) {
+          const uint32_t f = fb + uint32_t(lane);
           if (f < total) {
             int s = 0;  // last lane whose offset is <= f
 #pragma unroll
@@ -259,22 +280,21 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
         __builtin_amdgcn_wave_barrier();
         const uint64_t wb = uniform(wave_min_u64(lbest));
         best = wb < best ? wb : best;
-        cost += 1 + (total + kWave - 1) / kWave;
-        if (cost >= budget) break;  // high d: a shell can hold many row batches
       }
-      if (cost >= budget) {  // shell k may be incomplete: only the prefix scan is exact now
+      if (cost >= budget) {  // the annulus is incomplete: only the prefix scan is exact now
         defer = true;
         break;
       }
-      // The searched block is now every cell within k of the point's cell.
+      // The searched block is now every cell within k1 of the point's cell.
       int64_t gap = INT64_MAX;
 #pragma unroll
       for (int t = 0; t < D; ++t) {
-        if (c[t] - k >= 1) gap = min(gap, int64_t(x[t]) - int64_t(c[t] - k) * p.L + 1);
-        if (c[t] + k <= p.nc - 2) gap = min(gap, int64_t(c[t] + k + 1) * p.L - int64_t(x[t]));
+        if (c[t] - k1 >= 1) gap = min(gap, int64_t(x[t]) - int64_t(c[t] - k1) * p.L + 1);
+        if (c[t] + k1 <= p.nc - 2) gap = min(gap, int64_t(c[t] + k1 + 1) * p.L - int64_t(x[t]));
       }
       if (gap == INT64_MAX) break;  // the block covers the whole grid
       if (best != kNoKey && (best >> kIdBits) < uint64_t(gap) * uint64_t(gap)) break;
+      k0 = k1;
     }
     // Every lane stores the same values (no lane-divergent branch in the loop).
     w.best[id] = best;
@@ -289,16 +309,17 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
   const int lane = lane_id();
   const uint64_t npeaks = uniform(as_const(&w.hdr->n_peaks)[0]);
-  const uint64_t cpp = uint64_t((p.n + kPeakChunk - 1) / kPeakChunk);
+  // A prefix is split into at most kPeakSplit chunks of at least kPeakChunk candidates.
+  const uint64_t chunk = max(uint64_t(kPeakChunk), uint64_t((p.n + kPeakSplit - 1) / kPeakSplit));
+  const uint64_t cpp = uint64_t((p.n + chunk - 1) / chunk);
   const uint64_t units = npeaks * cpp;
   DPC_CONST(int32_t) *spc = as_const(w.spts);
   DPC_CONST(uint64_t) *sKc = as_const(w.sK);
   DPC_CONST(uint32_t) *peaks = as_const(w.peaks);
   DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
 
-  for (;;) {
-    const uint64_t u = uniform(static_cast<uint64_t>(atomicAdd(&w.hdr->peak_next, lane == 0 ? 1ull : 0ull)));
-    if (u >= units) break;
+  const uint32_t nw = grid_waves();
+  for (uint64_t u = wave_index(); u < units; u += nw) {
     const uint32_t pk = uint32_t(u / cpp);
     const uint64_t ch = u % cpp;
     const uint32_t q = uniform(peaks[pk]);
@@ -307,8 +328,8 @@ __global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
     const int64_t rho = int64_t(Ki >> 32);
     const uint32_t bstart = uniform(rstart[p.n - rho]);
     const uint32_t bend = uniform(rstart[p.n - rho + 1]);
-    const uint64_t r0 = ch * kPeakChunk;
-    const uint64_t r1 = min(r0 + kPeakChunk, uint64_t(bend));
+    const uint64_t r0 = ch * chunk;
+    const uint64_t r1 = min(r0 + chunk, uint64_t(bend));
     int32_t x[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) x[t] = uniform(spc[int64_t(q) * D + t]);

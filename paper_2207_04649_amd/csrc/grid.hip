@@ -189,13 +189,47 @@ __global__ void k_gather_rank_keys(Plan p, const int32_t *__restrict__ rho, cons
 
 // ---- density-rank sort: order by rho descending; equal rho share a bucket ----
 
-__global__ void k_rank_hist(Plan p, const uint64_t *__restrict__ sK, uint32_t *__restrict__ rcnt,
-                            uint32_t *__restrict__ slot) {
-  int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= p.n) return;
-  int64_t rho = int64_t(sK[q] >> 32);
-  rho = rho < 1 ? 1 : (rho > p.n ? p.n : rho);
-  slot[q] = atomicAdd(&rcnt[p.n - rho], 1u);
+// Bucket slots of the density-rank sort.  Most densities are small and many
+// points share one, so a block first counts its small densities in LDS and then
+// claims each bucket's slots with one global atomic; densities of kRankBins or
+// more take a global atomic each.
+constexpr int kRankBins = 2048;
+constexpr int kRankItems = 4;  // points per thread
+
+__global__ __launch_bounds__(kBlock) void k_rank_hist(Plan p, const uint64_t *__restrict__ sK,
+                                                      uint32_t *__restrict__ rcnt, uint32_t *__restrict__ slot) {
+  __shared__ uint32_t bins[kRankBins];
+  for (int b = threadIdx.x; b < kRankBins; b += kBlock) bins[b] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kBlock * kRankItems;
+  uint32_t local[kRankItems];
+  int64_t rho[kRankItems];
+#pragma unroll
+  for (int k = 0; k < kRankItems; ++k) {
+    const int64_t q = base + int64_t(k) * kBlock + threadIdx.x;
+    rho[k] = 0;
+    local[k] = 0;
+    if (q < p.n) {
+      int64_t r = int64_t(sK[q] >> 32);
+      r = r < 1 ? 1 : (r > p.n ? p.n : r);
+      rho[k] = r;
+      if (r <= kRankBins)
+        local[k] = atomicAdd(&bins[r - 1], 1u);
+      else
+        slot[q] = atomicAdd(&rcnt[p.n - r], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kRankBins; b += kBlock) {
+    const uint32_t c = bins[b];
+    if (c && b + 1 <= p.n) bins[b] = atomicAdd(&rcnt[p.n - (b + 1)], c);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRankItems; ++k) {
+    const int64_t q = base + int64_t(k) * kBlock + threadIdx.x;
+    if (q < p.n && rho[k] <= kRankBins) slot[q] = bins[rho[k] - 1] + local[k];
+  }
 }
 
 __global__ void k_rank_scatter(Plan p, const uint64_t *__restrict__ sK, const uint32_t *__restrict__ rstart,
@@ -279,7 +313,7 @@ hipError_t gather_rank_keys(const Plan &p, const Ws &w, const int32_t *rho, hipS
 hipError_t rank_sort(const Plan &p, const Ws &w, hipStream_t s) {
   hipError_t e;
   if ((e = launch_fill_u32(w.rcnt, 0u, p.n + 1, s)) != hipSuccess) return e;
-  DPC_LAUNCH((k_rank_hist), blocks_for(p.n, kBlock), kBlock, s, p, w.sK, w.rcnt, w.slot);
+  DPC_LAUNCH((k_rank_hist), blocks_for(p.n, kBlock * kRankItems), kBlock, s, p, w.sK, w.rcnt, w.slot);
   if ((e = launch_scan(w.rcnt, p.n + 1, w.bsum, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_rank_scatter), blocks_for(p.n, kBlock), kBlock, s, p, w.sK, w.rcnt, w.slot, w.spts, w.sid, w.rpts,
                                                            w.rid);
