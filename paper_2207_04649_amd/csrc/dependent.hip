@@ -32,6 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_ring1(Plan p, Ws w) {
   DPC_CONST(uint32_t) *spk = as_const(w.spk);
   DPC_CONST(int32_t) *spc = as_const(w.spts);
   DPC_CONST(uint64_t) *sKc = as_const(w.sK);
+  DPC_CONST(int32_t) *sidc = as_const(w.sid);
   const uint32_t ntasks = uniform(as_const(&w.hdr->ntasks)[0]);
 
   const uint32_t nw = grid_waves();
@@ -61,18 +62,25 @@ __global__ __launch_bounds__(kBlock) void k_ring1(Plan p, Ws w) {
         if (MODE == kModeP16) {
           constexpr int B = 8 / W > 0 ? 8 / W : 1;
           for (; j + B <= e; j += B) {
-            uint32_t c[B * W];
+            // one scalar load per array for B candidates (uniform base, constant offsets)
+            DPC_CONST(uint32_t) *cb = spk + int64_t(j) * W;
+            DPC_CONST(uint64_t) *kb = sKc + j;
+            DPC_CONST(int32_t) *ib = sidc + j;
+            uint32_t c[B * W], idj[B];
             uint64_t kj[B];
 #pragma unroll
-            for (int u = 0; u < B * W; ++u) c[u] = spk[int64_t(j) * W + u];
+            for (int u = 0; u < B * W; ++u) c[u] = cb[u];
 #pragma unroll
-            for (int u = 0; u < B; ++u) kj[u] = sKc[j + u];
+            for (int u = 0; u < B; ++u) {
+              kj[u] = kb[u];
+              idj[u] = uint32_t(ib[u]);
+            }
 #pragma unroll
             for (int u = 0; u < B; ++u) {
               int32_t d2 = dot2_self_s(pk_sub16(qk[0], c[u * W]), 0);
 #pragma unroll
               for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], c[u * W + k]), d2);
-              const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | uint32_t(~uint32_t(kj[u]));
+              const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | idj[u];
               best = (kj[u] > Ki && key < best) ? key : best;
             }
           }
@@ -81,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_ring1(Plan p, Ws w) {
             int32_t d2 = dot2_self_s(pk_sub16(qk[0], spk[int64_t(j) * W]), 0);
 #pragma unroll
             for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], spk[int64_t(j) * W + k]), d2);
-            const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | uint32_t(~uint32_t(kj));
+            const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | uint32_t(sidc[j]);
             best = (kj > Ki && key < best) ? key : best;
           }
         } else {
