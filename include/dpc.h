@@ -114,24 +114,28 @@ int64_t dpc_cutoff_square(double d_cut);
 
 /* The grid a call would use for these sizes, for diagnostics (host only, nothing enqueued). */
 typedef struct {
-  int64_t R;          /* ceil(d_cut^2) */
-  int64_t cell_side;  /* L >= floor(sqrt(R - 1)): the 3^d cells around a point hold its d_cut-ball */
+  int64_t R;             /* ceil(d_cut^2) */
+  int64_t cell_side;     /* L: cell side of the grid */
   int64_t cells_per_dim;
-  int64_t cells;      /* cells_per_dim^d, the dense cell table */
-  int64_t strip_cells;/* cells per strip along the last dimension */
+  int64_t cells;         /* cells_per_dim^d, the dense cell table */
+  int64_t strip_cells;   /* cells per strip along the last dimension */
   int64_t strips;
   int64_t max_tasks;
-  int64_t mode;       /* 0: packed 16-bit distance path; 1: exact int64 path */
+  int64_t mode;          /* density kernel: 0 packed 16-bit distance path, 1 exact int64 path */
   int64_t workspace_bytes;
+  int64_t window_radius; /* K0 cells: K0 * L >= floor(sqrt(R - 1)), so (2 K0 + 1)^d cells hold a d_cut-ball */
+  int64_t stages;        /* dependent-search stages */
 } dpc_plan_info;
 dpc_status dpc_plan(int64_t n, int32_t d, double d_cut, dpc_plan_info *out);
 
-/* Kernel timing for diagnostics: when enabled, every call records HIP events on its stream
- * around each kernel group (grid_build, density, rank_keys, rank_sort, ring1, ringk, peaks,
- * finish, label).  dpc_profile_report waits for them, writes
- * {"group": [launches, total_ms], ...} as JSON into buf (up to len bytes, NUL-terminated),
- * returns the full length, and clears the records. */
-void dpc_profile_enable(int32_t on);
+/* Kernel timing for diagnostics.  Level 1: every call records HIP events on its stream
+ * around each kernel group (grid_build, density, rank_keys, rank_sort, search, ringk, peaks,
+ * finish, label).  Level 2 also synchronises after each dependent search and keeps its work
+ * counters (tasks, points left open by the search stages, points sent to the prefix scan,
+ * candidates those scans cover).  Level 0 turns it off.  dpc_profile_report waits for the
+ * events, writes {"group": [launches, total_ms], ..., "work": {...}} as JSON into buf (up to
+ * len bytes, NUL-terminated), returns the full length, and clears the records. */
+void dpc_profile_enable(int32_t level);
 int32_t dpc_profile_report(char *buf, size_t len);
 
 /* Synchronises `stream` and returns the device-detected status of the most recent call on

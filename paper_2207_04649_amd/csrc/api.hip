@@ -22,12 +22,14 @@ struct ProfRec {
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof_recs;
 std::vector<ProfRec> g_prof_open;  // begins awaiting their end, per kernel id
-bool g_prof_enabled = false;
-const char *kProfNames[kProfCount] = {"grid_build", "density", "rank_keys", "rank_sort", "ring1",
+int g_prof_level = 0;
+// work counters of the last dependent search (profiling level 2)
+int64_t g_work[4] = {0, 0, 0, 0};
+const char *kProfNames[kProfCount] = {"grid_build", "density", "rank_keys", "rank_sort", "search",
                                       "ringk", "peaks", "finish", "label"};
 }  // namespace
 
-bool prof_on() { return g_prof_enabled; }
+bool prof_on() { return g_prof_level > 0; }
 
 void prof_mark(hipStream_t s, int kernel, bool begin) {
   hipEvent_t e;
@@ -115,6 +117,10 @@ int64_t p16_extent(int d) {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Cells per ball half-extent for each dimension (finer cells clip the windows
+// closer to the d_cut-ball; the table grows as their d-th power).
+int default_subdivision(int d) { return d <= 2 ? 4 : (d == 3 ? 2 : 1); }
+
 bool make_plan(int64_t n, int32_t d, double d_cut, Plan *out) {
   if (n < 1 || n >= DPC_MAX_POINTS || d < 1 || d > DPC_MAX_DIM) return false;
   const int64_t R = cutoff_square(d_cut);
@@ -125,19 +131,36 @@ bool make_plan(int64_t n, int32_t d, double d_cut, Plan *out) {
   p.d = d;
   p.words = (d + 1) / 2;
   p.R = R;
-  int64_t L = isqrt64(R - 1);
-  if (L < 1) L = 1;
-  int64_t nc = (DPC_COORD_LIMIT + L - 1) / L;
-  // Coarsen the cells until the dense table fits; any side >= floor(sqrt(R - 1)) stays exact.
+  int64_t L0 = isqrt64(R - 1);
+  if (L0 < 1) L0 = 1;
+  if (L0 > DPC_COORD_LIMIT) L0 = DPC_COORD_LIMIT;
+  p.L0 = int32_t(L0);
+  int S = default_subdivision(d);
+  if (const char *env = std::getenv("DPC_SUBDIV")) {  // tuning override
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= 16) S = v;
+  }
   const int64_t nc_max = iroot(kTableMax, d);
-  if (nc > nc_max) {
+  int64_t L = 1, nc = 1;
+  for (;; --S) {
+    L = (L0 + S - 1) / S;
+    if (L < 1) L = 1;
+    nc = (DPC_COORD_LIMIT + L - 1) / L;
+    if (nc <= nc_max || S == 1) break;
+  }
+  if (nc > nc_max) {  // coarsen: any side >= floor(sqrt(R - 1)) stays exact
     L = (DPC_COORD_LIMIT + nc_max - 1) / nc_max;
     nc = (DPC_COORD_LIMIT + L - 1) / L;
   }
   p.L = int32_t(L);
   p.nc = int32_t(nc);
-  const int64_t wc16 = p16_extent(d) / L - 2;
-  if (wc16 >= 1) {
+  p.K0 = int32_t((L0 + L - 1) / L);
+  // Strip width: a window of radius K around a strip spans at most (wc + 2K)
+  // cells in the last dimension; the packed 16-bit path needs that below E.
+  const int64_t E = p16_extent(d);
+  auto p16_ok = [&](int64_t K, int64_t wc) { return wc >= 1 && (wc + 2 * K) * L <= E && (2 * K + 1) * L <= E; };
+  const int64_t wc16 = E / L - 2 * int64_t(p.K0);
+  if (p16_ok(p.K0, wc16)) {
     p.mode = kModeP16;
     p.wc = int32_t(wc16 < nc ? wc16 : nc);
   } else {
@@ -147,6 +170,40 @@ bool make_plan(int64_t n, int32_t d, double d_cut, Plan *out) {
   if (const char *env = std::getenv("DPC_STRIP_CELLS")) {  // tuning override (narrower only)
     int64_t v = std::atoll(env);
     if (v >= 1 && v < p.wc) p.wc = int32_t(v);
+  }
+  // Dependent-search stages: window radii in cells and tasks gathered per wave
+  // (more as fewer points stay open); a later stage is dropped when its window
+  // has more than 4096 rows.
+  int radii[4] = {1, 4, 0, 0}, groups[4] = {1, 4, 0, 0}, nst = 2;
+  if (const char *env = std::getenv("DPC_STAGES")) {  // tuning override: "K:group,K:group,..."
+    int k = 0;
+    for (const char *c = env; *c && k < 4;) {
+      int K = 0, g = 1;
+      if (std::sscanf(c, "%d:%d", &K, &g) < 1 || K < 1 || K > 64 || g < 1 || g > 64) break;
+      radii[k] = K;
+      groups[k] = g;
+      ++k;
+      c = std::strchr(c, ',');
+      if (!c) break;
+      ++c;
+    }
+    if (k > 0) nst = k;
+  }
+  p.nstages = 0;
+  for (int st = 0; st < nst; ++st) {
+    const int K = radii[st];
+    int64_t rows = 1;
+    for (int t = 0; t < d - 1; ++t) rows *= 2 * K + 1;
+    if (st > 0 && rows > 4096) break;
+    p.stageK[p.nstages] = K;
+    p.stageGroup[p.nstages] = groups[st];
+    p.stageMode[p.nstages] = p16_ok(K, p.wc) ? kModeP16 : kModeI64;
+    ++p.nstages;
+  }
+  p.ring_cap = kRingCostCap;
+  if (const char *env = std::getenv("DPC_RING_CAP")) {  // tuning override
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= 1 << 20) p.ring_cap = v;
   }
   p.nsx = int32_t((nc + p.wc - 1) / p.wc);
   p.ncells = ipow(nc, d);
@@ -178,6 +235,7 @@ bool make_plan(int64_t n, int32_t d, double d_cut, Plan *out) {
   p.o_best = take(size_t(n) * 8);
   p.o_unres = take(size_t(n + 1) * 4);  // + a spare slot for lanes that append nothing
   p.o_peaks = take(size_t(n + 1) * 4);
+  p.o_flag = take(size_t(n));
   p.total = o;
   *out = p;
   return true;
@@ -207,6 +265,29 @@ dpc_status run_density(const Plan &p, const Ws &w, const int32_t *pts, int32_t *
   return DPC_OK;
 }
 
+// Profiling level 2: tasks, points left open by the search stages, points sent
+// to the prefix scan and the candidates those scans cover (synchronises).
+hipError_t record_work(const Plan &p, const Ws &w, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  DevHeader h;
+  if ((e = hipMemcpy(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  std::vector<uint32_t> peaks(h.n_peaks), rstart(size_t(p.n) + 1);
+  std::vector<uint64_t> sK(size_t(p.n));
+  if (h.n_peaks && (e = hipMemcpy(peaks.data(), w.peaks, h.n_peaks * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+    return e;
+  if ((e = hipMemcpy(sK.data(), w.sK, sK.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  if ((e = hipMemcpy(rstart.data(), w.rcnt, rstart.size() * 4, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  int64_t prefix = 0;
+  for (uint32_t q : peaks) prefix += rstart[size_t(p.n - int64_t(sK[q] >> 32) + 1)];
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_work[0] = h.ntasks;
+  g_work[1] = h.n_unres;
+  g_work[2] = h.n_peaks;
+  g_work[3] = prefix;
+  return hipSuccess;
+}
+
 dpc_status run_dependent(const Plan &p, const Ws &w, const int32_t *pts, const int32_t *rho, int32_t *dep,
                          double *delta, bool reuse, hipStream_t s) {
   hipError_t e;
@@ -225,6 +306,7 @@ dpc_status run_dependent(const Plan &p, const Ws &w, const int32_t *pts, const i
     if ((e = rank_sort(p, w, s)) != hipSuccess) return device_fail(e, "rank sort");
   }
   if ((e = launch_dependent(p, w, dep, delta, s)) != hipSuccess) return device_fail(e, "dependent kernels");
+  if (g_prof_level >= 2 && (e = record_work(p, w, s)) != hipSuccess) return device_fail(e, "work counters");
   return DPC_OK;
 }
 
@@ -259,6 +341,8 @@ dpc_status dpc_plan(int64_t n, int32_t d, double d_cut, dpc_plan_info *out) {
   out->max_tasks = p.max_tasks;
   out->mode = p.mode;
   out->workspace_bytes = int64_t(p.total);
+  out->window_radius = p.K0;
+  out->stages = p.nstages;
   return DPC_OK;
 }
 
@@ -325,9 +409,9 @@ dpc_status dpc_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32
   return DPC_OK;
 }
 
-void dpc_profile_enable(int32_t on) {
+void dpc_profile_enable(int32_t level) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_enabled = on != 0;
+  g_prof_level = level < 0 ? 0 : level;
 }
 
 int32_t dpc_profile_report(char *buf, size_t len) {
@@ -352,6 +436,14 @@ int32_t dpc_profile_report(char *buf, size_t len) {
     char item[128];
     std::snprintf(item, sizeof(item), "%s\"%s\": [%lld, %.6f]", k ? ", " : "", kProfNames[k],
                   static_cast<long long>(calls[k]), ms[k]);
+    out += item;
+  }
+  {
+    char item[192];
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::snprintf(item, sizeof(item), ", \"work\": {\"tasks\": %lld, \"open\": %lld, \"peaks\": %lld, "
+                  "\"peak_prefix\": %lld}", static_cast<long long>(g_work[0]), static_cast<long long>(g_work[1]),
+                  static_cast<long long>(g_work[2]), static_cast<long long>(g_work[3]));
     out += item;
   }
   out += "}";

@@ -23,7 +23,7 @@ constexpr int kScanItems = 16;           // items per thread in the block scan
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kPeakChunk = 8192;         // least candidates per peak work unit
 constexpr int kPeakSplit = 16;           // most work units per peak
-constexpr int kRingCostCap = 48;         // most ring-search steps per point before the prefix scan
+constexpr int kRingCostCap = 48;         // default of Plan::ring_cap
 
 enum DistMode : int32_t {
   kModeP16 = 0,  // low 16 bits of each coordinate, packed two per word; exact while the
@@ -34,15 +34,10 @@ enum DistMode : int32_t {
 // Device-side scalars of one workspace.  Counters are reset by the call that uses them.
 struct DevHeader {
   uint32_t status;        // errors of the current call: bit 0 coordinate out of range, bit 1 inconsistent input
-  uint32_t ntasks;        // tasks of the density / ring-1 kernels (written by the task builder)
-  uint32_t task_next;     // work counter, density kernel
-  uint32_t task_next2;    // work counter, ring-1 kernel
-  uint32_t n_unres;       // points left unresolved by ring-1
-  uint32_t unres_next;    // work counter, ring-k kernel
+  uint32_t ntasks;        // tasks of the density and search kernels (written by the task builder)
+  uint32_t n_unres;       // points left open by the search stages
   uint32_t n_peaks;       // points left to the rank-prefix scan
-  uint32_t pad0;
-  unsigned long long peak_next;  // work counter, peak kernel ((peak, chunk) units)
-  uint32_t pad[54];
+  uint32_t pad[60];
 };
 static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
 
@@ -52,19 +47,25 @@ struct Plan {
   int32_t d;
   int32_t words;     // packed 16-bit words per point, (d + 1) / 2
   int64_t R;         // ceil(d_cut^2)
+  int32_t L0;        // floor(sqrt(R - 1)): largest coordinate gap inside the d_cut-ball
+  int32_t K0;        // density window radius in cells: K0 * L >= L0
   int32_t L;         // cell side
   int32_t nc;        // cells per dimension
   int32_t wc;        // strip width in cells along the last dimension
   int32_t nsx;       // strips per row, ceil(nc / wc)
-  int32_t mode;      // DistMode
-  int32_t pad0;
+  int32_t mode;      // DistMode of the density kernel
+  int32_t nstages;   // dependent-search stages
+  int32_t stageK[4];     // window radius (cells) of each stage
+  int32_t stageGroup[4]; // tasks gathered per wave in each stage
+  int32_t stageMode[4];  // DistMode of each stage
+  int32_t ring_cap;  // most ring-search steps per point before the prefix scan
   int64_t ncells;    // nc^d
   int64_t nrows;     // nc^(d-1)
   int64_t nstrips;   // nrows * nsx
   int64_t max_tasks;
   // workspace byte offsets
   size_t o_hdr, o_cnt, o_bsum, o_key, o_slot, o_spts, o_spk, o_sid, o_sK, o_tcnt, o_tasks, o_rcnt,
-      o_rpts, o_rid, o_best, o_unres, o_peaks, total;
+      o_rpts, o_rid, o_best, o_unres, o_peaks, o_flag, total;
 };
 
 // Pointers into one workspace, resolved from a Plan.
@@ -84,8 +85,9 @@ struct Ws {
   int32_t *rpts;     // [n][d] coordinates in rank order
   int32_t *rid;      // [n] id at each rank position
   uint64_t *best;    // [n] packed (D2 << 27 | dep) per id, kNoKey if none
-  uint32_t *unres;   // [n + 1] cell-order positions unresolved after ring 1 (+ spare slot)
+  uint32_t *unres;   // [n + 1] cell-order positions open after the search stages (+ spare slot)
   uint32_t *peaks;   // [n + 1] cell-order positions left to the rank-prefix scan (+ spare slot)
+  uint8_t *flag;     // [n] 1 while the cell-order position's dependent point is open
 };
 
 inline Ws resolve(const Plan &p, void *base) {
@@ -108,6 +110,7 @@ inline Ws resolve(const Plan &p, void *base) {
   w.best = reinterpret_cast<uint64_t *>(b + p.o_best);
   w.unres = reinterpret_cast<uint32_t *>(b + p.o_unres);
   w.peaks = reinterpret_cast<uint32_t *>(b + p.o_peaks);
+  w.flag = reinterpret_cast<uint8_t *>(b + p.o_flag);
   return w;
 }
 

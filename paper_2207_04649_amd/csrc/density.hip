@@ -1,12 +1,13 @@
 // Local density (Def. 1, Eq. 1): rho_i = #{ j : D2(i, j) < R }, the point itself
 // included, R = ceil(d_cut^2).
 //
-// One wave per task (64 queries, one per lane).  The wave walks its window's
+// One wave per task (64 queries, one per lane).  The window holds the cells
+// within K0 of the task's cells (K0 * L >= floor(sqrt(R - 1)), so it covers every
+// d_cut-ball) and is clipped to the balls' union row by row.  The wave walks its
 // candidate runs with scalar loads, so every candidate reaches all 64 lanes as a
-// scalar operand; no LDS, no barriers.  Tasks are handed out by a global work
-// counter, so the cost spread between dense and sparse cells balances
-// dynamically (the paper's dynamic per-point scheduling, Section 3, in
-// wave-sized units).  Waves take tasks in a static interleave (see wave_index).
+// scalar operand: no LDS, no barriers.  Waves take tasks in a static interleave
+// (see wave_index); the paper balances the per-point range searches with dynamic
+// OpenMP scheduling (Section 3), the interleave does it in wave-sized units.
 #include "tasks.h"
 
 namespace dpc {
@@ -18,29 +19,35 @@ __global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w, int32_t *__res
   const int lane = lane_id();
   DPC_CONST(uint32_t) *spk = as_const(w.spk);
   DPC_CONST(int32_t) *spc = as_const(w.spts);
-  DPC_CONST(uint32_t) *start = as_const(w.cnt);
+  DPC_CONST(uint32_t) *tc = as_const(reinterpret_cast<const uint32_t *>(w.tasks));
   const uint32_t ntasks = uniform(as_const(&w.hdr->ntasks)[0]);
   const int32_t negR = -int32_t(p.R < INT32_MAX ? p.R : INT32_MAX);
+  const int K = p.K0;
+  const uint64_t clip2 = uint64_t(p.R - 1);  // D2 <= R - 1 is inside the ball
+  int nrow = 1;
+  for (int t = 0; t < D - 1; ++t) nrow *= 2 * K + 1;
 
   const uint32_t nw = grid_waves();
   for (uint32_t t = wave_index(); t < ntasks; t += nw) {
-    const TaskGeom<D> g = decode_task<D>(p, w.tasks, w.spts, t);
-    const uint32_t q = min(g.qb + uint32_t(lane), g.qe - 1u);
-    uint32_t qk[W];
+    const uint32_t qb = uniform(uint32_t(tc[4 * int64_t(t)]));
+    const uint32_t qe = uniform(uint32_t(tc[4 * int64_t(t) + 1]));
+    TaskGeom<D> g;
+    strip_row<D>(p, uniform(uint32_t(tc[4 * int64_t(t) + 2])), g);
+    const uint32_t q = min(qb + uint32_t(lane), qe - 1u);
     int32_t qx[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) qx[k] = w.spts[int64_t(q) * D + k];
+    task_span<D>(p, g, qx[D - 1], true);
+    uint32_t qk[W];
     if (MODE == kModeP16) {
 #pragma unroll
       for (int k = 0; k < W; ++k) qk[k] = w.spk[int64_t(q) * W + k];
-    } else {
-#pragma unroll
-      for (int k = 0; k < D; ++k) qx[k] = w.spts[int64_t(q) * D + k];
     }
     uint32_t count = 0;
-    constexpr int NROW = Pow3<D - 1>::value;
-    for (int rb = 0; rb < NROW; rb += kWave) {
+    for (int rb = 0; rb < nrow; rb += kWave) {
       uint32_t sb = 0, se = 0;
-      if (rb + lane < NROW) window_row<D>(p, g, rb + lane, w.cnt, &sb, &se);
-      const int nr = min(kWave, NROW - rb);
+      if (rb + lane < nrow) window_row<D>(p, g, K, rb + lane, clip2, w.cnt, &sb, &se);
+      const int nr = min(kWave, nrow - rb);
       for (int r = 0; r < nr; ++r) {
         const uint32_t b = __builtin_amdgcn_readlane(sb, r);
         const uint32_t e = __builtin_amdgcn_readlane(se, r);
@@ -48,9 +55,10 @@ __global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w, int32_t *__res
         if (MODE == kModeP16) {
           constexpr int B = 16 / W;
           for (; j + B <= e; j += B) {
+            DPC_CONST(uint32_t) *cb = spk + int64_t(j) * W;
             uint32_t c[B * W];
 #pragma unroll
-            for (int u = 0; u < B * W; ++u) c[u] = spk[int64_t(j) * W + u];
+            for (int u = 0; u < B * W; ++u) c[u] = cb[u];
 #pragma unroll
             for (int u = 0; u < B; ++u) {
               int32_t acc = dot2_self_s(pk_sub16(qk[0], c[u * W]), negR);

@@ -2,18 +2,20 @@
 //
 // q_i is the point with the smallest (D2, id) among the points ranked above i in
 // the order (rho descending, id ascending); delta_i = sqrt(D2).  Ex-DPC finds it
-// with a kd-tree grown in density order (Section 3); here it takes three exact
-// passes, all keyed by the packed u64 (D2 << 27 | id), whose minimum is unique,
-// so every reduction order gives the same answer:
+// with a kd-tree grown in density order (Section 3); here it takes exact passes,
+// all keyed by the packed u64 (D2 << 27 | id), whose minimum is unique, so every
+// reduction order gives the same answer:
 //
-//  1. ring 1: each task (64 queries) scans its density window; a query whose best
-//     candidate is strictly closer than the window's exterior is final.  Most
-//     points end here, since most dependent distances are below d_cut (Section 3,
-//     after Lemma 2);
-//  2. ring k: one wave per remaining point grows the searched cell block one
-//     shell at a time, skipping cells farther than the best so far, until the
-//     best is strictly closer than the block's exterior, or the remaining work
-//     would exceed a scan of the point's density prefix;
+//  1. search stages: windows of radius K = 1, 4, 16 cells around groups of up to
+//     64 open points of one strip.  A point whose best candidate is strictly
+//     closer than its window's exterior is final.  Most points end in the first
+//     stage, since most dependent distances are far below d_cut (the paper makes
+//     the same observation, Section 3, after Lemma 2); later stages gather the
+//     open points of several tasks into full waves and clip their windows to the
+//     largest best distance found so far;
+//  2. ring search: one wave per still-open point grows the searched cell block
+//     by annuli, until the best is strictly closer than the block's exterior or
+//     the work would exceed a scan of the point's density prefix;
 //  3. peaks: a scan of the density prefix (the points of higher rank, contiguous
 //     in the rank-sorted copy, as in the straightforward algorithm of Section 2.2,
 //     step 3), split over waves and merged with a 64-bit atomic minimum.
@@ -23,99 +25,186 @@
 namespace dpc {
 namespace {
 
-// -------------------------------------------------------------------- ring 1
+// -------------------------------------------------------------------- search stages
 
+// One window search for up to 64 open points of one strip (lane = point; lanes
+// with valid = false repeat a valid lane's point and store the same values).
 template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_ring1(Plan p, Ws w) {
+__device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int K, bool first, uint32_t strip,
+                                             uint32_t q, bool valid) {
   constexpr int W = (D + 1) / 2;
   const int lane = lane_id();
   DPC_CONST(uint32_t) *spk = as_const(w.spk);
   DPC_CONST(int32_t) *spc = as_const(w.spts);
   DPC_CONST(uint64_t) *sKc = as_const(w.sK);
   DPC_CONST(int32_t) *sidc = as_const(w.sid);
-  const uint32_t ntasks = uniform(as_const(&w.hdr->ntasks)[0]);
-
-  const uint32_t nw = grid_waves();
-  for (uint32_t t = wave_index(); t < ntasks; t += nw) {
-    const TaskGeom<D> g = decode_task<D>(p, w.tasks, w.spts, t);
-    const uint32_t q = min(g.qb + uint32_t(lane), g.qe - 1u);
-    const uint64_t Ki = w.sK[q];
-    int32_t qx[D];
+  TaskGeom<D> g;
+  strip_row<D>(p, strip, g);
+  int32_t qx[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) qx[k] = w.spts[int64_t(q) * D + k];
-    uint32_t qk[W];
-    if (MODE == kModeP16) {
+  for (int k = 0; k < D; ++k) qx[k] = w.spts[int64_t(q) * D + k];
+  task_span<D>(p, g, qx[D - 1], valid);
+  const uint64_t Ki = w.sK[q];
+  const uint32_t id = uint32_t(~uint32_t(Ki));
+  uint64_t best = first ? kNoKey : w.best[id];
+  // Clip the window to the largest best distance when every point has one.
+  const bool all_have = __ballot(valid && best == kNoKey) == 0;
+  uint64_t clip2 = ~uint64_t(0);
+  if (all_have) clip2 = uniform(wave_max_u64(valid ? (best >> kIdBits) : uint64_t(0)));
+  uint32_t qk[W];
+  if (MODE == kModeP16) {
 #pragma unroll
-      for (int k = 0; k < W; ++k) qk[k] = w.spk[int64_t(q) * W + k];
-    }
-    // P16: best = (D2 << 32) | id (D2 < 2^31); I64: best = (D2 << 27) | id.
-    uint64_t best = kNoKey;
-    constexpr int NROW = Pow3<D - 1>::value;
-    for (int rb = 0; rb < NROW; rb += kWave) {
-      uint32_t sb = 0, se = 0;
-      if (rb + lane < NROW) window_row<D>(p, g, rb + lane, w.cnt, &sb, &se);
-      const int nr = min(kWave, NROW - rb);
-      for (int r = 0; r < nr; ++r) {
-        const uint32_t b = __builtin_amdgcn_readlane(sb, r);
-        const uint32_t e = __builtin_amdgcn_readlane(se, r);
-        uint32_t j = b;
-        if (MODE == kModeP16) {
-          constexpr int B = 8 / W > 0 ? 8 / W : 1;
-          for (; j + B <= e; j += B) {
-            // one scalar load per array for B candidates (uniform base, constant offsets)
-            DPC_CONST(uint32_t) *cb = spk + int64_t(j) * W;
-            DPC_CONST(uint64_t) *kb = sKc + j;
-            DPC_CONST(int32_t) *ib = sidc + j;
-            uint32_t c[B * W], idj[B];
-            uint64_t kj[B];
+    for (int k = 0; k < W; ++k) qk[k] = w.spk[int64_t(q) * W + k];
+    // inner-loop key: (D2 << 32) | id, D2 < 2^31 on this path
+    if (best != kNoKey) best = ((best >> kIdBits) << 32) | (best & kIdMask);
+  }
+  int nrow = 1;
+  for (int t = 0; t < D - 1; ++t) nrow *= 2 * K + 1;
+  for (int rb = 0; rb < nrow; rb += kWave) {
+    uint32_t sb = 0, se = 0;
+    if (rb + lane < nrow) window_row<D>(p, g, K, rb + lane, clip2, w.cnt, &sb, &se);
+    const int nr = min(kWave, nrow - rb);
+    for (int r = 0; r < nr; ++r) {
+      const uint32_t b = __builtin_amdgcn_readlane(sb, r);
+      const uint32_t e = __builtin_amdgcn_readlane(se, r);
+      uint32_t j = b;
+      if (MODE == kModeP16) {
+        constexpr int B = 8 / W > 0 ? 8 / W : 1;
+        for (; j + B <= e; j += B) {
+          // one scalar load per array for B candidates (uniform base, constant offsets)
+          DPC_CONST(uint32_t) *cb = spk + int64_t(j) * W;
+          DPC_CONST(uint64_t) *kb = sKc + j;
+          DPC_CONST(int32_t) *ib = sidc + j;
+          uint32_t c[B * W], idj[B];
+          uint64_t kj[B];
 #pragma unroll
-            for (int u = 0; u < B * W; ++u) c[u] = cb[u];
+          for (int u = 0; u < B * W; ++u) c[u] = cb[u];
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-              kj[u] = kb[u];
-              idj[u] = uint32_t(ib[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < B; ++u) {
-              int32_t d2 = dot2_self_s(pk_sub16(qk[0], c[u * W]), 0);
-#pragma unroll
-              for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], c[u * W + k]), d2);
-              const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | idj[u];
-              best = (kj[u] > Ki && key < best) ? key : best;
-            }
+          for (int u = 0; u < B; ++u) {
+            kj[u] = kb[u];
+            idj[u] = uint32_t(ib[u]);
           }
-          for (; j < e; ++j) {
-            const uint64_t kj = sKc[j];
-            int32_t d2 = dot2_self_s(pk_sub16(qk[0], spk[int64_t(j) * W]), 0);
 #pragma unroll
-            for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], spk[int64_t(j) * W + k]), d2);
-            const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | uint32_t(sidc[j]);
-            best = (kj > Ki && key < best) ? key : best;
-          }
-        } else {
-          for (; j < e; ++j) {
-            const uint64_t kj = sKc[j];
-            int64_t d2 = 0;
+          for (int u = 0; u < B; ++u) {
+            int32_t d2 = dot2_self_s(pk_sub16(qk[0], c[u * W]), 0);
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-              const int64_t df = int64_t(qx[k] - spc[int64_t(j) * D + k]);
-              d2 += df * df;
-            }
-            const uint64_t key = (uint64_t(d2) << kIdBits) | uint32_t(~uint32_t(kj));
-            best = (kj > Ki && key < best) ? key : best;
+            for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], c[u * W + k]), d2);
+            const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | idj[u];
+            best = (kj[u] > Ki && key < best) ? key : best;
           }
+        }
+        for (; j < e; ++j) {
+          const uint64_t kj = sKc[j];
+          int32_t d2 = dot2_self_s(pk_sub16(qk[0], spk[int64_t(j) * W]), 0);
+#pragma unroll
+          for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], spk[int64_t(j) * W + k]), d2);
+          const uint64_t key = (uint64_t(uint32_t(d2)) << 32) | uint32_t(sidc[j]);
+          best = (kj > Ki && key < best) ? key : best;
+        }
+      } else {
+        for (; j < e; ++j) {
+          const uint64_t kj = sKc[j];
+          int64_t d2 = 0;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const int64_t df = int64_t(qx[k] - spc[int64_t(j) * D + k]);
+            d2 += df * df;
+          }
+          const uint64_t key = (uint64_t(d2) << kIdBits) | uint32_t(sidc[j]);
+          best = (kj > Ki && key < best) ? key : best;
         }
       }
     }
-    if (MODE == kModeP16 && best != kNoKey) best = ((best >> 32) << kIdBits) | (best & 0xFFFFFFFFu);
-    const uint64_t ext = window_exterior_d2<D>(p, g, qx);
-    const bool resolved = ext == kNoKey || (best != kNoKey && (best >> kIdBits) < ext);
-    // Lanes past the end of the task repeat its last query (same values, same
-    // places); only valid lanes append, and the others write the spare slot n.
-    const bool take = g.qb + uint32_t(lane) < g.qe && !resolved;
-    w.best[uint32_t(~uint32_t(Ki))] = best;
-    const uint32_t slot = wave_append(&w.hdr->n_unres, take);
-    w.unres[take ? slot : uint32_t(p.n)] = q;
+  }
+  if (MODE == kModeP16 && best != kNoKey) best = ((best >> 32) << kIdBits) | (best & 0xFFFFFFFFu);
+  const uint64_t ext = window_exterior_d2<D>(p, g, K, qx);
+  const bool resolved = ext == kNoKey || (best != kNoKey && (best >> kIdBits) < ext);
+  w.best[id] = best;
+  w.flag[q] = resolved ? 0 : 1;
+}
+
+// One search stage.  Each wave takes `group` consecutive tasks, gathers their
+// open points (all points in the first stage) into batches of 64 per strip
+// through an LDS queue, and searches each batch's window of radius K.
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_search(Plan p, Ws w, int K, int group, int first) {
+  __shared__ uint32_t queue_all[kWavesPerBlock][2 * kWave + 1];  // + a spare slot
+  uint32_t *queue = queue_all[threadIdx.x / kWave];
+  const int lane = lane_id();
+  DPC_CONST(uint32_t) *tc = as_const(reinterpret_cast<const uint32_t *>(w.tasks));
+  const uint32_t ntasks = uniform(as_const(&w.hdr->ntasks)[0]);
+  const uint32_t ngroups = (ntasks + uint32_t(group) - 1) / uint32_t(group);
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+
+  const uint32_t nw = grid_waves();
+  for (uint32_t gi = wave_index(); gi < ngroups; gi += nw) {
+    uint32_t pending = 0, cur = 0;
+    const uint32_t t_end = min((gi + 1) * uint32_t(group), ntasks);
+    for (uint32_t t = gi * uint32_t(group); t < t_end; ++t) {
+      const uint32_t qb = uniform(uint32_t(tc[4 * int64_t(t)]));
+      const uint32_t qe = uniform(uint32_t(tc[4 * int64_t(t) + 1]));
+      const uint32_t strip = uniform(uint32_t(tc[4 * int64_t(t) + 2]));
+      if (pending != 0 && strip != cur) {  // a batch never spans two strips
+        const uint32_t qv = queue[min(uint32_t(lane), pending - 1)];
+        search_batch<D, MODE>(p, w, K, first != 0, cur, qv, uint32_t(lane) < pending);
+        pending = 0;
+      }
+      cur = strip;
+      const uint32_t q = qb + uint32_t(lane);
+      const bool take = q < qe && (first != 0 || w.flag[min(q, qe - 1)] != 0);
+      const uint64_t m = __ballot(take);
+      queue[take ? pending + uint32_t(__popcll(m & below)) : uint32_t(2 * kWave)] = q;
+      pending += uint32_t(__popcll(m));
+      __builtin_amdgcn_wave_barrier();
+      if (pending >= uint32_t(kWave)) {
+        search_batch<D, MODE>(p, w, K, first != 0, cur, queue[lane], true);
+        const uint32_t moved = queue[kWave + lane];  // entries kWave.. move to the front
+        __builtin_amdgcn_wave_barrier();
+        queue[lane] = moved;
+        __builtin_amdgcn_wave_barrier();
+        pending -= uint32_t(kWave);
+      }
+    }
+    if (pending != 0) {
+      const uint32_t qv = queue[min(uint32_t(lane), pending - 1)];
+      search_batch<D, MODE>(p, w, K, first != 0, cur, qv, uint32_t(lane) < pending);
+    }
+  }
+}
+
+// Open points after the search stages, as a list in cell order.  Each thread
+// reads kCollectPer flags; a block counts its open points, takes its slice of
+// the list with one atomic and writes it in order (one atomic per block: a
+// counter that every wave bumps serialises in L2).
+constexpr int kCollectPer = 16;
+
+__global__ __launch_bounds__(kBlock) void k_collect(Plan p, const uint8_t *__restrict__ flag,
+                                                    uint32_t *__restrict__ unres, DevHeader *__restrict__ hdr) {
+  __shared__ uint32_t wave_tot[kWavesPerBlock];
+  __shared__ uint32_t base;
+  const int64_t i0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * kCollectPer;
+  uint32_t open = 0;
+#pragma unroll
+  for (int k = 0; k < kCollectPer; ++k) {
+    const int64_t i = i0 + k;
+    open |= (i < p.n && flag[i < p.n ? i : 0] != 0) ? (1u << k) : 0u;
+  }
+  uint32_t tot;
+  const uint32_t off = wave_exclusive_scan(uint32_t(__popc(open)), &tot);
+  const int wv = threadIdx.x / kWave;
+  wave_tot[wv] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t sum = 0;
+    for (int k = 0; k < kWavesPerBlock; ++k) sum += wave_tot[k];
+    base = atomicAdd(&hdr->n_unres, sum);
+  }
+  __syncthreads();
+  uint32_t at = base + off;
+  for (int k = 0; k < wv; ++k) at += wave_tot[k];
+#pragma unroll
+  for (int k = 0; k < kCollectPer; ++k) {
+    if (open & (1u << k)) unres[at++] = uint32_t(i0 + k);
   }
 }
 
@@ -154,16 +243,9 @@ __device__ __forceinline__ uint64_t exact_d2_v(const int32_t *a, const int32_t *
   return uint64_t(s);
 }
 
-// Largest r with r * r <= v (v < 2^38).
-__device__ __forceinline__ int64_t isqrt_floor(uint64_t v) {
-  int64_t r = int64_t(__builtin_sqrt(double(v)));
-  while (r > 0 && uint64_t(r) * uint64_t(r) > v) --r;
-  while (uint64_t(r + 1) * uint64_t(r + 1) <= v) ++r;
-  return r;
-}
-
-// Ring search for the points ring 1 left open.  The searched block grows from
-// the cells within k0 = 1 of the point's cell to k1 = 2 k0 (an annulus per
+// Ring search for the points the search stages left open.  The searched block
+// grows from the cells within k0 (the last stage's radius) of the point's cell
+// to k1 = 2 k0 (an annulus per
 // pass, so a sparse neighbourhood needs a logarithmic number of passes).  In
 // every row of the annulus the cell range is clipped to the cells that can
 // still hold a point within the best distance so far, and a row farther than
@@ -171,7 +253,7 @@ __device__ __forceinline__ int64_t isqrt_floor(uint64_t v) {
 // closer than the exterior of the block; it goes to the prefix scan when the
 // passes have cost more than that scan would.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
+__global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w, int k_start) {
   __shared__ SegLds lds_all[kWavesPerBlock];
   SegLds &lds = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
@@ -195,10 +277,10 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
     const int64_t rho = int64_t(Ki >> 32);
     uint64_t best = uniform(w.best[id]);
     const uint32_t prefix = uniform(rstart[p.n - rho + 1]);
-    const int64_t budget = min(int64_t(prefix / kWave) + 2, int64_t(kRingCostCap));
+    const int64_t budget = min(int64_t(prefix / kWave) + 2, int64_t(p.ring_cap));
     int64_t cost = 0;
     bool defer = false;
-    int32_t k0 = 1;
+    int32_t k0 = k_start;
 
     for (;;) {
       const int32_t k1 = 2 * k0;
@@ -304,10 +386,13 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w) {
       if (best != kNoKey && (best >> kIdBits) < uint64_t(gap) * uint64_t(gap)) break;
       k0 = k1;
     }
-    // Every lane stores the same values (no lane-divergent branch in the loop).
+    // Every lane stores the same values (no lane-divergent branch in the loop);
+    // `defer` is wave-uniform, so its branch is a scalar one.
     w.best[id] = best;
-    const uint32_t slot = uniform(wave_append(&w.hdr->n_peaks, defer && lane == 0));
-    w.peaks[defer ? slot : uint32_t(p.n)] = q;
+    if (uniform(defer ? 1u : 0u) != 0u) {
+      const uint32_t slot = uniform(wave_append(&w.hdr->n_peaks, lane == 0));
+      w.peaks[slot] = q;
+    }
   }
 }
 
@@ -376,18 +461,22 @@ __global__ void k_finish(Plan p, const uint64_t *__restrict__ best, int32_t *__r
 
 template <int D>
 hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta, hipStream_t s) {
-  const unsigned tb = persistent_blocks(p.max_tasks);
   {
-    ProfScope ps(s, kProfRing1);
-    if (p.mode == kModeP16)
-      DPC_LAUNCH((k_ring1<D, kModeP16>), tb, kBlock, s, p, w);
-    else
-      DPC_LAUNCH((k_ring1<D, kModeI64>), tb, kBlock, s, p, w);
+    ProfScope ps(s, kProfSearch);
+    for (int st = 0; st < p.nstages; ++st) {
+      const int K = p.stageK[st], group = p.stageGroup[st];
+      const unsigned blocks = persistent_blocks((p.max_tasks + group - 1) / group);
+      if (p.stageMode[st] == kModeP16)
+        DPC_LAUNCH((k_search<D, kModeP16>), blocks, kBlock, s, p, w, K, group, st == 0 ? 1 : 0);
+      else
+        DPC_LAUNCH((k_search<D, kModeI64>), blocks, kBlock, s, p, w, K, group, st == 0 ? 1 : 0);
+    }
   }
   const unsigned rb = persistent_blocks(p.n);
   {
     ProfScope ps(s, kProfRingK);
-    DPC_LAUNCH((k_ringk<D>), rb, kBlock, s, p, w);
+    DPC_LAUNCH((k_collect), blocks_for(p.n, kBlock * kCollectPer), kBlock, s, p, w.flag, w.unres, w.hdr);
+    DPC_LAUNCH((k_ringk<D>), rb, kBlock, s, p, w, p.stageK[p.nstages - 1]);
   }
   {
     ProfScope ps(s, kProfPeaks);

@@ -253,12 +253,8 @@ __global__ void k_clear_status(DevHeader *hdr) {
 __global__ void k_reset_counters(DevHeader *hdr, int grid) {
   if (threadIdx.x == 0) {
     if (grid) hdr->ntasks = 0;
-    hdr->task_next = 0;
-    hdr->task_next2 = 0;
     hdr->n_unres = 0;
-    hdr->unres_next = 0;
     hdr->n_peaks = 0;
-    hdr->peak_next = 0;
   }
 }
 

@@ -11,7 +11,7 @@ enum ProfKernel : int {
   kProfDensity,
   kProfRankKeys,
   kProfRankSort,
-  kProfRing1,
+  kProfSearch,
   kProfRingK,
   kProfPeaks,
   kProfFinish,

@@ -1,11 +1,17 @@
-// Task geometry shared by the density and ring-1 kernels.
+// Task geometry shared by the density and dependent-search kernels.
 //
-// A task is up to 64 consecutive cell-order points of one strip (cells x0..x1 of
-// one row).  Its search window is, in every row adjacent to the query row
-// (3^(d-1) rows), the contiguous cell range [x0 - 1, x1 + 1]: it contains the
-// 3^d cells around every query's own cell, so it holds every point closer than
-// d_cut to any query (Def. 1).  Cells are keyed row-major, so each of those row
-// ranges is one contiguous run of the cell-ordered arrays.
+// A task is up to 64 cell-order points of one strip (cells of one row of the
+// grid, all coordinates but the last fixed).  Its search window of radius K
+// cells is, in every row within K of the task's row ((2K+1)^(d-1) rows), the
+// contiguous cell range [x0 - K, x1 + K], where x0..x1 are the last-dimension
+// cells of the task's points.  Cells are keyed row-major, so each row range is
+// one contiguous run of the cell-ordered arrays.
+//
+// Rows and row ranges are clipped to a radius when one is known: a row whose
+// nearest coordinate is farther than the radius from the task's row is
+// skipped, and the cell range is cut to the cells within the radius of the
+// task's last-coordinate span.  With the cut-off distance as the radius (local
+// density, Def. 1) the window follows the d_cut-ball instead of its bounding box.
 #pragma once
 
 #include "common.h"
@@ -13,79 +19,122 @@
 namespace dpc {
 
 template <int D>
-struct Pow3 {
-  static constexpr int value = 3 * Pow3<D - 1>::value;
-};
-template <>
-struct Pow3<0> {
-  static constexpr int value = 1;
-};
-
-template <int D>
 struct TaskGeom {
-  uint32_t qb, qe;     // query positions [qb, qe)
-  int32_t c[D > 1 ? D - 1 : 1];  // cell coordinates of the query row
-  int32_t x0, x1;      // last-dimension cells of the first and last query
+  int32_t c[D > 1 ? D - 1 : 1];  // cell coordinates of the task's row
+  int32_t x0, x1;                // last-dimension cells of the task's points
+  int32_t xlo, xhi;              // last-dimension coordinate span of the task's points
 };
 
-// Decode task t (all values uniform across the wave).
+// Row coordinates of strip `strip`.
 template <int D>
-__device__ __forceinline__ TaskGeom<D> decode_task(const Plan &p, const uint4 *tasks, const int32_t *spts,
-                                                   uint32_t t) {
-  TaskGeom<D> g;
-  DPC_CONST(uint32_t) *tc = as_const(reinterpret_cast<const uint32_t *>(tasks));
-  g.qb = uniform(uint32_t(tc[4 * int64_t(t)]));
-  g.qe = uniform(uint32_t(tc[4 * int64_t(t) + 1]));
-  int64_t row = int64_t(uniform(uint32_t(tc[4 * int64_t(t) + 2]))) / p.nsx;
+__device__ __forceinline__ void strip_row(const Plan &p, uint32_t strip, TaskGeom<D> &g) {
+  int64_t row = int64_t(strip) / p.nsx;
 #pragma unroll
-  for (int t2 = D - 2; t2 >= 0; --t2) {
-    g.c[t2] = int32_t(row % p.nc);
+  for (int t = D - 2; t >= 0; --t) {
+    g.c[t] = int32_t(row % p.nc);
     row /= p.nc;
   }
-  DPC_CONST(int32_t) *sp = as_const(spts);
-  g.x0 = uniform(sp[int64_t(g.qb) * D + (D - 1)] / p.L);
-  g.x1 = uniform(sp[int64_t(g.qe - 1) * D + (D - 1)] / p.L);
-  return g;
 }
 
-// Candidate range of row offset r (0 <= r < 3^(D-1)) of a task's window; empty
-// if the row lies outside the grid.
+// Squared distance from the task's row to row offset o of a window (0 for the
+// row itself): the gap between the row cells, per dimension, summed.
+__device__ __forceinline__ int64_t row_gap(int32_t o, int32_t L) {
+  const int32_t a = o < 0 ? -o : o;
+  return a == 0 ? 0 : int64_t(a - 1) * L + 1;
+}
+
+// Largest r with r * r <= v (v < 2^62).
+__device__ __forceinline__ int64_t isqrt_floor(uint64_t v) {
+  int64_t r = int64_t(__builtin_sqrt(double(v)));
+  while (r > 0 && uint64_t(r) * uint64_t(r) > v) --r;
+  while (uint64_t(r + 1) * uint64_t(r + 1) <= v) ++r;
+  return r;
+}
+
+// Candidate range [b, e) of row r (0 <= r < (2K+1)^(D-1)) of the window of
+// radius K, clipped to squared radius `clip2` (no clipping when clip2 is
+// UINT64_MAX).  Empty if the row is outside the grid or beyond the radius.
 template <int D>
-__device__ __forceinline__ void window_row(const Plan &p, const TaskGeom<D> &g, int r, const uint32_t *start,
-                                           uint32_t *b, uint32_t *e) {
-  int64_t rowk = 0;
-  bool ok = true;
-#pragma unroll
-  for (int t = 0; t < D - 1; ++t) {
-    const int32_t nb = g.c[t] + (r % 3) - 1;
-    r /= 3;
-    ok = ok && nb >= 0 && nb < p.nc;
-    rowk = rowk * p.nc + nb;
-  }
+__device__ __forceinline__ void window_row(const Plan &p, const TaskGeom<D> &g, int K, int r, uint64_t clip2,
+                                           const uint32_t *start, uint32_t *b, uint32_t *e) {
   *b = 0;
   *e = 0;
-  if (ok) {
-    const int64_t klo = rowk * p.nc + max(g.x0 - 1, 0);
-    const int64_t khi = rowk * p.nc + min(g.x1 + 1, p.nc - 1);
-    *b = start[klo];
-    *e = start[khi + 1];
+  int64_t rowk = 0, dy2 = 0;
+  bool ok = true;
+  const int side = 2 * K + 1;
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) {
+    const int32_t o = r % side - K;
+    r /= side;
+    const int32_t nb = g.c[t] + o;
+    ok = ok && nb >= 0 && nb < p.nc;
+    rowk = rowk * p.nc + nb;
+    const int64_t gy = row_gap(o, p.L);
+    dy2 += gy * gy;
   }
+  if (!ok) return;
+  int32_t lo = max(g.x0 - K, 0), hi = min(g.x1 + K, p.nc - 1);
+  if (clip2 != ~uint64_t(0)) {
+    if (uint64_t(dy2) > clip2) return;
+    const int64_t hw = isqrt_floor(clip2 - uint64_t(dy2));
+    lo = max(lo, int32_t(max(int64_t(g.xlo) - hw, int64_t(0)) / p.L));
+    hi = min(hi, int32_t(min(int64_t(g.xhi) + hw, int64_t(DPC_COORD_LIMIT - 1)) / p.L));
+    if (lo > hi) return;
+  }
+  *b = start[rowk * p.nc + lo];
+  *e = start[rowk * p.nc + hi + 1];
 }
 
-// Squared distance from a query to the outside of its task window, as a bound:
-// every point outside the window has D2 >= the returned value (kNoKey-like
-// UINT64_MAX when the window reaches the grid boundary on every side).
+// Squared distance from a point to the outside of the unclipped window of
+// radius K: every point outside has D2 >= the returned value (UINT64_MAX when
+// the window reaches the grid boundary on every side).
 template <int D>
-__device__ __forceinline__ uint64_t window_exterior_d2(const Plan &p, const TaskGeom<D> &g, const int32_t *x) {
+__device__ __forceinline__ uint64_t window_exterior_d2(const Plan &p, const TaskGeom<D> &g, int K, const int32_t *x) {
   int64_t gap = INT64_MAX;
 #pragma unroll
   for (int t = 0; t < D; ++t) {
-    const int32_t lo = (t == D - 1) ? g.x0 - 1 : g.c[t] - 1;
-    const int32_t hi = (t == D - 1) ? g.x1 + 1 : g.c[t] + 1;
+    const int32_t lo = (t == D - 1) ? g.x0 - K : g.c[t] - K;
+    const int32_t hi = (t == D - 1) ? g.x1 + K : g.c[t] + K;
     if (lo >= 1) gap = min(gap, int64_t(x[t]) - int64_t(lo) * p.L + 1);
     if (hi <= p.nc - 2) gap = min(gap, int64_t(hi + 1) * p.L - int64_t(x[t]));
   }
   return gap == INT64_MAX ? ~uint64_t(0) : uint64_t(gap) * uint64_t(gap);
+}
+
+// Wave-wide minimum / maximum of a 32-bit value.
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(v, off, kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Finish a task's geometry from its points' last coordinates (lanes holding a
+// valid point pass valid = true; all 64 lanes call this).
+template <int D>
+__device__ __forceinline__ void task_span(const Plan &p, TaskGeom<D> &g, int32_t xlast, bool valid) {
+  g.xlo = uniform(wave_min_i32(valid ? xlast : INT32_MAX));
+  g.xhi = uniform(wave_max_i32(valid ? xlast : INT32_MIN));
+  g.x0 = g.xlo / p.L;
+  g.x1 = g.xhi / p.L;
 }
 
 }  // namespace dpc

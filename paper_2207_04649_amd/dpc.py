@@ -33,7 +33,7 @@ class DpcError(RuntimeError):
 class PlanInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "R", "cell_side", "cells_per_dim", "cells", "strip_cells", "strips", "max_tasks", "mode",
-        "workspace_bytes")]
+        "workspace_bytes", "window_radius", "stages")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -55,13 +55,14 @@ def test_plan_invariants(n, d, d_cut):
     p = dpc.dpc_plan(n, d, d_cut)
     R = min(math.ceil(Fraction(d_cut) ** 2), 1 << 38)
     assert p["R"] == R
-    L = p["cell_side"]
-    assert L >= max(1, math.isqrt(R - 1)), "3^d cells must hold the d_cut-ball"
+    L, K0 = p["cell_side"], p["window_radius"]
+    assert K0 * L >= min(max(1, math.isqrt(R - 1)), dpc.COORD_LIMIT), "(2 K0 + 1)^d cells must hold the d_cut-ball"
     assert p["cells_per_dim"] * L >= dpc.COORD_LIMIT
     assert p["cells"] == p["cells_per_dim"] ** d <= 1 << 26
     if p["mode"] == 0:  # packed 16-bit path: window extent keeps |dx| < 2^15 and D2 < 2^31
-        E = (p["strip_cells"] + 2) * L
+        E = (p["strip_cells"] + 2 * K0) * L
         assert E - 1 <= 32767 and d * (E - 1) ** 2 <= 2 ** 31 - 1
+    assert p["stages"] >= 1
     assert p["workspace_bytes"] == dpc.dpc_workspace_bytes(n, d, d_cut) > 0
 
 
