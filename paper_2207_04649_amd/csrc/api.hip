@@ -174,7 +174,7 @@ bool make_plan(int64_t n, int32_t d, double d_cut, Plan *out) {
   // Dependent-search stages: window radii in cells and tasks gathered per wave
   // (more as fewer points stay open); a later stage is dropped when its window
   // has more than 4096 rows.
-  int radii[4] = {1, 4, 0, 0}, groups[4] = {1, 4, 0, 0}, nst = 2;
+  int radii[4] = {1, 3, 0, 0}, groups[4] = {1, 4, 0, 0}, nst = 2;
   if (const char *env = std::getenv("DPC_STAGES")) {  // tuning override: "K:group,K:group,..."
     int k = 0;
     for (const char *c = env; *c && k < 4;) {

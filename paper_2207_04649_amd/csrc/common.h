@@ -21,8 +21,7 @@ constexpr uint64_t kIdMask = (uint64_t(1) << kIdBits) - 1;
 constexpr uint64_t kNoKey = ~uint64_t(0);
 constexpr int kScanItems = 16;           // items per thread in the block scan
 constexpr int kScanTile = kBlock * kScanItems;
-constexpr int kPeakChunk = 8192;         // least candidates per peak work unit
-constexpr int kPeakSplit = 16;           // most work units per peak
+constexpr int kPeakChunk = 256;          // rank-order candidates per prefix-scan work unit
 constexpr int kRingCostCap = 48;         // default of Plan::ring_cap
 
 enum DistMode : int32_t {

@@ -6,19 +6,20 @@
 // all keyed by the packed u64 (D2 << 27 | id), whose minimum is unique, so every
 // reduction order gives the same answer:
 //
-//  1. search stages: windows of radius K = 1, 4, 16 cells around groups of up to
-//     64 open points of one strip.  A point whose best candidate is strictly
-//     closer than its window's exterior is final.  Most points end in the first
-//     stage, since most dependent distances are far below d_cut (the paper makes
-//     the same observation, Section 3, after Lemma 2); later stages gather the
-//     open points of several tasks into full waves and clip their windows to the
-//     largest best distance found so far;
+//  1. search stages: windows of radius K = 1 and 3 cells (by default) around
+//     groups of up to 64 open points of one strip.  A point whose best candidate
+//     is strictly closer than its window's exterior is final.  Most points end
+//     in the first stage, since most dependent distances are far below d_cut
+//     (the paper makes the same observation, Section 3, after Lemma 2); later
+//     stages gather the open points of several tasks into full waves and clip
+//     their windows to the largest best distance found so far;
 //  2. ring search: one wave per still-open point grows the searched cell block
 //     by annuli, until the best is strictly closer than the block's exterior or
 //     the work would exceed a scan of the point's density prefix;
 //  3. peaks: a scan of the density prefix (the points of higher rank, contiguous
 //     in the rank-sorted copy, as in the straightforward algorithm of Section 2.2,
-//     step 3), split over waves and merged with a 64-bit atomic minimum.
+//     step 3), 64 points per wave, split over waves in chunks and merged with a
+//     64-bit atomic minimum.
 #include "prof.h"
 #include "tasks.h"
 
@@ -398,48 +399,94 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w, int k_start) {
 
 // -------------------------------------------------------------------- peaks
 
+// Prefix scan for the points the ring search deferred.  A work unit is 64
+// deferred points (one per lane) and one chunk of kPeakChunk positions of the
+// rank-sorted copy; the wave streams the chunk with scalar loads, so each
+// candidate is loaded once for 64 points.  Lane i takes candidate r when r ranks
+// above it: r before its density bucket, or in its bucket with a smaller id
+// (buckets are unordered inside).  Units are spread over all waves, and each
+// lane merges its chunk minimum into best[] with a 64-bit atomic minimum.
+template <int D>
+__device__ __forceinline__ void peak_batch_load(DPC_CONST(int32_t) * rpc, DPC_CONST(int32_t) * ridc, uint32_t r,
+                                                int32_t *c, int32_t *idr) {
+  constexpr int B = 16 / D > 0 ? 16 / D : 1;
+  DPC_CONST(int32_t) *cb = rpc + int64_t(r) * D;
+  DPC_CONST(int32_t) *ib = ridc + r;
+#pragma unroll
+  for (int v = 0; v < B * D; ++v) c[v] = cb[v];
+#pragma unroll
+  for (int v = 0; v < B; ++v) idr[v] = ib[v];
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
+  constexpr int B = 16 / D > 0 ? 16 / D : 1;  // candidates per scalar-load batch
   const int lane = lane_id();
-  const uint64_t npeaks = uniform(as_const(&w.hdr->n_peaks)[0]);
-  // A prefix is split into at most kPeakSplit chunks of at least kPeakChunk candidates.
-  const uint64_t chunk = max(uint64_t(kPeakChunk), uint64_t((p.n + kPeakSplit - 1) / kPeakSplit));
-  const uint64_t cpp = uint64_t((p.n + chunk - 1) / chunk);
-  const uint64_t units = npeaks * cpp;
-  DPC_CONST(int32_t) *spc = as_const(w.spts);
-  DPC_CONST(uint64_t) *sKc = as_const(w.sK);
-  DPC_CONST(uint32_t) *peaks = as_const(w.peaks);
-  DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
+  const uint32_t npeaks = uniform(as_const(&w.hdr->n_peaks)[0]);
+  const uint32_t ngroups = (npeaks + kWave - 1) / kWave;
+  const uint32_t nchunks = uint32_t((p.n + kPeakChunk - 1) / kPeakChunk);
+  const uint64_t units = uint64_t(ngroups) * nchunks;
+  DPC_CONST(int32_t) *rpc = as_const(w.rpts);
+  DPC_CONST(int32_t) *ridc = as_const(w.rid);
 
   const uint32_t nw = grid_waves();
   for (uint64_t u = wave_index(); u < units; u += nw) {
-    const uint32_t pk = uint32_t(u / cpp);
-    const uint64_t ch = u % cpp;
-    const uint32_t q = uniform(peaks[pk]);
-    const uint64_t Ki = uniform(sKc[q]);
-    const uint32_t id = uint32_t(~uint32_t(Ki));
+    const uint32_t g = uint32_t(u % ngroups);
+    const uint32_t ch = uint32_t(u / ngroups);
+    const uint32_t q = w.peaks[min(g * uint32_t(kWave) + uint32_t(lane), npeaks - 1u)];
+    const uint64_t Ki = w.sK[q];
+    const int32_t id = int32_t(~uint32_t(Ki));
     const int64_t rho = int64_t(Ki >> 32);
-    const uint32_t bstart = uniform(rstart[p.n - rho]);
-    const uint32_t bend = uniform(rstart[p.n - rho + 1]);
-    const uint64_t r0 = ch * chunk;
-    const uint64_t r1 = min(r0 + chunk, uint64_t(bend));
+    const uint32_t bstart = w.rcnt[p.n - rho];
+    const uint32_t bend = w.rcnt[p.n - rho + 1];
+    const uint32_t r0 = ch * uint32_t(kPeakChunk);
+    const uint32_t r1 = min(r0 + uint32_t(kPeakChunk), uint32_t(uniform(wave_max_i32(int32_t(bend)))));
+    if (r0 >= r1) continue;  // wave-uniform: the chunk lies past every lane's prefix
     int32_t x[D];
 #pragma unroll
-    for (int t = 0; t < D; ++t) x[t] = uniform(spc[int64_t(q) * D + t]);
+    for (int t = 0; t < D; ++t) x[t] = w.spts[int64_t(q) * D + t];
     uint64_t lbest = kNoKey;
-    for (uint64_t r = r0 + lane; r < r1; r += kWave) {
-      const uint32_t j = uint32_t(w.rid[r]);
-      if (r < bstart || j < id) {
-        int32_t y[D];
+    uint32_t r = r0;
+    if (r + B <= r1) {
+      int32_t c[B * D], idr[B];
+      peak_batch_load<D>(rpc, ridc, r, c, idr);
+      for (;;) {
+        // Load the next batch (or this one again at the end) before using this one.
+        const uint32_t rn = r + B;
+        const bool more = rn + B <= r1;
+        int32_t cn[B * D], idn[B];
+        peak_batch_load<D>(rpc, ridc, more ? rn : r, cn, idn);
 #pragma unroll
-        for (int t = 0; t < D; ++t) y[t] = w.rpts[r * D + t];
-        const uint64_t key = (exact_d2_v<D>(x, y) << kIdBits) | j;
-        lbest = key < lbest ? key : lbest;
+        for (int v = 0; v < B; ++v) {
+          const uint32_t rv = r + uint32_t(v);
+          // rank above: before the bucket, or inside it with a smaller id (no short circuit)
+          const bool above = (rv < bstart) | ((rv < bend) & (idr[v] < id));
+          const uint64_t key = (exact_d2_v<D>(x, c + v * D) << kIdBits) | uint32_t(idr[v]);
+          lbest = (above & (key < lbest)) ? key : lbest;
+        }
+        r = rn;
+        if (!more) break;
+#pragma unroll
+        for (int v = 0; v < B * D; ++v) c[v] = cn[v];
+#pragma unroll
+        for (int v = 0; v < B; ++v) idr[v] = idn[v];
       }
     }
-    // All lanes merge the same wave minimum (kNoKey leaves the entry unchanged).
-    const uint64_t wb = wave_min_u64(lbest);
-    atomicMin(reinterpret_cast<unsigned long long *>(&w.best[id]), static_cast<unsigned long long>(wb));
+    for (; r < r1; ++r) {
+      int32_t c[D];
+#pragma unroll
+      for (int t = 0; t < D; ++t) c[t] = rpc[int64_t(r) * D + t];
+      const int32_t idr = ridc[r];
+      const bool above = (r < bstart) | ((r < bend) & (idr < id));
+      const uint64_t key = (exact_d2_v<D>(x, c) << kIdBits) | uint32_t(idr);
+      lbest = (above & (key < lbest)) ? key : lbest;
+    }
+    // Only lanes that hold a point of the list and found a candidate merge: lanes
+    // past the end repeat the last point, and atomics of many lanes on one
+    // address serialise in L2.  (A plain if-region: no loop depends on it.)
+    const bool own = g * uint32_t(kWave) + uint32_t(lane) < npeaks;
+    if (own && lbest != kNoKey)
+      atomicMin(reinterpret_cast<unsigned long long *>(&w.best[id]), static_cast<unsigned long long>(lbest));
   }
 }
 

@@ -277,6 +277,7 @@ inline T emu_readlane(T v, int l) {
 #define __builtin_amdgcn_wave_barrier() ((void)emu::wave_exchange(0))
 #define __builtin_amdgcn_fence(...) ((void)0)
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
+inline int __popc(unsigned v) { return __builtin_popcount(v); }
 inline int __ffsll(long long v) { return __builtin_ffsll(v); }
 
 template <class T>
