@@ -38,6 +38,35 @@ def density_ops(d: int) -> int:
     return 2 * d + 2
 
 
+# HBM bytes of the density kernel per launch, from two rocprofv3 --pmc runs of
+# this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the
+# kernel's dispatches).  A plain 256 MiB device copy read back 131088.4 KiB of
+# FETCH_SIZE and a 256 MiB fill wrote 262144 KiB of WRITE_SIZE, so fetches are
+# scaled by 262144 / 131088.4 and writes by 1.  The figures belong to the kernel
+# sources they were taken with: if those change, traffic is reported as null.
+DENSITY_SOURCES = ("paper_2207_04649_amd/csrc/density.hip", "paper_2207_04649_amd/csrc/tasks.h",
+                   "paper_2207_04649_amd/csrc/common.h")
+DENSITY_HBM = {"blobs_1m_d2": {"source": "71cdbab751e8182e", "fetch_kib": 50779.2, "write_kib": 44902.5}}
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.4375, 1.0
+
+
+def source_hash(files) -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def density_traffic(workload: str):
+    rec = DENSITY_HBM.get(workload)
+    if rec is None or rec["source"] != source_hash(DENSITY_SOURCES):
+        return None
+    return (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE) * 1024.0
+
+
 def cpu_baseline(job, budget_s: float) -> dict:
     """The C oracle (plain O(n^2) scan) on a uniform subsample of the workload.
 
@@ -77,6 +106,9 @@ def main() -> int:
     ap.add_argument("--workload", default="blobs_1m_d2")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a plain copy kernel of known size, "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -92,6 +124,12 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         return 1
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     job = inputs.WORKLOADS[args.workload]()
     dev = torch.device("cuda:0")
     pts = torch.from_numpy(job.pts).to(dev)
@@ -129,7 +167,7 @@ def main() -> int:
     evals = sum_rho
     achieved = evals * density_ops(job.d) / (per["density"] * 1e-3) / 1e12
     roof = {"kernel": "density", "avg_ms": per["density"], "bound": "alu", "achieved": achieved,
-            "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+            "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": density_traffic(job.name),
             "evals_per_launch": evals, "ops_per_eval": density_ops(job.d), "slowest_group": dom}
 
     line = {

@@ -248,3 +248,7 @@ def check_full_size(dpc, job, n_rho=1500, n_dep=160, seed=0):
 
 def test_blobs_1m_sampled(dpc):
     check_full_size(dpc, inputs.blobs_1m())
+
+
+def test_walks_4m_sampled(dpc):
+    check_full_size(dpc, inputs.walks_4m(), n_rho=1000, n_dep=40)
