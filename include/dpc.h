@@ -145,6 +145,61 @@ int32_t dpc_profile_report(char *buf, size_t len);
  * status; this call clears it too. */
 dpc_status dpc_sync_status(void *ws, void *stream);
 
+/* Plan options of one problem (0 in any field: the library's default).  The defaults
+ * also take overrides from the environment (DPC_SUBDIV, DPC_STRIP_CELLS, DPC_STAGES
+ * "K:group,...", DPC_RING_CAP) for tuning experiments; explicit options win. */
+typedef struct {
+  int32_t subdiv;          /* cells per cut-off distance along each axis (1..16) */
+  int32_t strip_cells;     /* narrower task strips (cells along the last axis) */
+  int32_t nstages;         /* dependent-search window stages (1..4), radii and groups below */
+  int32_t stage_radius[4]; /* window radius of each stage in cells (1..64) */
+  int32_t stage_group[4];  /* tasks whose open points one wave gathers (1..64) */
+  int32_t ring_cap;        /* most ring-search steps per point before the prefix scan */
+} dpc_tuning;
+
+/* dpc_plan with explicit options (tuning may be NULL). */
+dpc_status dpc_plan_tuned(int64_t n, int32_t d, double d_cut, const dpc_tuning *tuning, dpc_plan_info *out);
+
+/*
+ * Many problems in one launch per phase (Definitions 1-6 for each job, as dpc_run).
+ *
+ * A job names its own points, thresholds and outputs (device pointers, caller-owned,
+ * as for dpc_run; distinct jobs must not share output arrays).  dpc_batch_plan checks
+ * every job as dpc_run would (the first bad job's index is in dpc_last_error), plans
+ * each one (`tuning`: NULL or one entry per job), orders the jobs by dimension and then
+ * by size, largest first, and returns a host handle and the workspace size.
+ * dpc_batch_bind writes the device job table into `ws` (a synchronous copy, so not
+ * inside graph capture).  dpc_batch_run then enqueues every phase for all jobs on
+ * `stream`, one launch per phase and dimension (no allocation, no host synchronisation:
+ * it can be captured in a HIP graph and replayed); it may run any number of times on
+ * the bound workspace.  Each job's results are those dpc_run gives for it alone.
+ */
+typedef struct {
+  const int32_t *pts; /* [n][d] int32, device */
+  int64_t n;
+  int32_t d;
+  double d_cut;
+  int32_t rho_min;
+  double delta_min;
+  int32_t *rho, *dep; /* [n] int32 outputs, device */
+  double *delta;      /* [n] double output, device */
+  int32_t *label;     /* [n] int32 output, device */
+  int64_t *ncenters;  /* device int64 output */
+} dpc_job;
+
+typedef struct dpc_batch dpc_batch; /* host-side plan of a batch */
+
+dpc_status dpc_batch_plan(const dpc_job *jobs, int32_t njobs, const dpc_tuning *tuning, dpc_batch **out,
+                          size_t *ws_bytes);
+dpc_status dpc_batch_bind(dpc_batch *batch, void *ws, size_t ws_bytes);
+dpc_status dpc_batch_run(const dpc_batch *batch, void *ws, void *stream);
+/* Synchronises and ORs the device status of every job (as dpc_sync_status); *first_bad
+ * (may be NULL) gets the caller's index of the first job with a non-zero status, or -1. */
+dpc_status dpc_batch_sync_status(const dpc_batch *batch, void *ws, void *stream, int32_t *first_bad);
+/* Plan of job i (the caller's index) of the batch. */
+dpc_status dpc_batch_job_plan(const dpc_batch *batch, int32_t i, dpc_plan_info *out);
+void dpc_batch_free(dpc_batch *batch);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *dpc_last_error(void);
 

@@ -1,8 +1,11 @@
 // The C ABI (include/dpc.h): argument checks, the exact cut-off, the grid plan,
 // the workspace layout and the launch sequence of each call.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <numeric>
 #include <string>
 
 #include "common.h"
@@ -121,10 +124,51 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 // closer to the d_cut-ball; the table grows as their d-th power).
 int default_subdivision(int d) { return d <= 2 ? 4 : (d == 3 ? 2 : 1); }
 
-bool make_plan(int64_t n, int32_t d, double d_cut, Plan *out) {
+// Options from the environment (tuning experiments); 0 = not set.
+dpc_tuning env_tuning() {
+  dpc_tuning t;
+  std::memset(&t, 0, sizeof(t));
+  if (const char *env = std::getenv("DPC_SUBDIV")) t.subdiv = std::atoi(env);
+  if (const char *env = std::getenv("DPC_STRIP_CELLS")) t.strip_cells = std::atoi(env);
+  if (const char *env = std::getenv("DPC_RING_CAP")) t.ring_cap = std::atoi(env);
+  if (const char *env = std::getenv("DPC_STAGES")) {  // "K:group,K:group,..."
+    int k = 0;
+    for (const char *c = env; *c && k < 4;) {
+      int K = 0, g = 1;
+      if (std::sscanf(c, "%d:%d", &K, &g) < 1) break;
+      t.stage_radius[k] = K;
+      t.stage_group[k] = g;
+      ++k;
+      c = std::strchr(c, ',');
+      if (!c) break;
+      ++c;
+    }
+    t.nstages = k;
+  }
+  return t;
+}
+
+bool valid_stages(const dpc_tuning &t) {
+  if (t.nstages < 1 || t.nstages > 4) return false;
+  for (int k = 0; k < t.nstages; ++k)
+    if (t.stage_radius[k] < 1 || t.stage_radius[k] > 64 || t.stage_group[k] < 1 || t.stage_group[k] > 64)
+      return false;
+  return true;
+}
+
+// Dense-table cap: at most kTableMax cells, and at most 8 per point (4096 at
+// least), so a small problem does not scan a table far larger than itself.
+int64_t table_cap(int64_t n) {
+  const int64_t c = std::max<int64_t>(4096, 8 * n);
+  return std::min<int64_t>(kTableMax, c);
+}
+
+bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *out) {
   if (n < 1 || n >= DPC_MAX_POINTS || d < 1 || d > DPC_MAX_DIM) return false;
   const int64_t R = cutoff_square(d_cut);
   if (R < 1) return false;
+  const dpc_tuning env = env_tuning();
+  auto pick = [&](int32_t explicit_v, int32_t env_v) { return explicit_v ? explicit_v : env_v; };
   Plan p;
   std::memset(&p, 0, sizeof(p));
   p.n = n;
@@ -136,11 +180,11 @@ bool make_plan(int64_t n, int32_t d, double d_cut, Plan *out) {
   if (L0 > DPC_COORD_LIMIT) L0 = DPC_COORD_LIMIT;
   p.L0 = int32_t(L0);
   int S = default_subdivision(d);
-  if (const char *env = std::getenv("DPC_SUBDIV")) {  // tuning override
-    const int v = std::atoi(env);
+  {
+    const int v = pick(opt ? opt->subdiv : 0, env.subdiv);
     if (v >= 1 && v <= 16) S = v;
   }
-  const int64_t nc_max = iroot(kTableMax, d);
+  const int64_t nc_max = iroot(table_cap(n), d);
   int64_t L = 1, nc = 1;
   for (;; --S) {
     L = (L0 + S - 1) / S;
@@ -167,42 +211,40 @@ bool make_plan(int64_t n, int32_t d, double d_cut, Plan *out) {
     p.mode = kModeI64;
     p.wc = int32_t(nc);
   }
-  if (const char *env = std::getenv("DPC_STRIP_CELLS")) {  // tuning override (narrower only)
-    int64_t v = std::atoll(env);
-    if (v >= 1 && v < p.wc) p.wc = int32_t(v);
+  {
+    const int64_t v = pick(opt ? opt->strip_cells : 0, env.strip_cells);
+    if (v >= 1 && v < p.wc) p.wc = int32_t(v);  // narrower only
   }
   // Dependent-search stages: window radii in cells and tasks gathered per wave
   // (more as fewer points stay open); a later stage is dropped when its window
   // has more than 4096 rows.
-  int radii[4] = {1, 3, 0, 0}, groups[4] = {1, 4, 0, 0}, nst = 2;
-  if (const char *env = std::getenv("DPC_STAGES")) {  // tuning override: "K:group,K:group,..."
-    int k = 0;
-    for (const char *c = env; *c && k < 4;) {
-      int K = 0, g = 1;
-      if (std::sscanf(c, "%d:%d", &K, &g) < 1 || K < 1 || K > 64 || g < 1 || g > 64) break;
-      radii[k] = K;
-      groups[k] = g;
-      ++k;
-      c = std::strchr(c, ',');
-      if (!c) break;
-      ++c;
-    }
-    if (k > 0) nst = k;
+  dpc_tuning st;
+  std::memset(&st, 0, sizeof(st));
+  st.nstages = 2;
+  st.stage_radius[0] = 1;
+  st.stage_group[0] = 1;
+  st.stage_radius[1] = 3;
+  st.stage_group[1] = 4;
+  if (opt && opt->nstages) {
+    if (!valid_stages(*opt)) return false;
+    st = *opt;
+  } else if (env.nstages && valid_stages(env)) {
+    st = env;
   }
   p.nstages = 0;
-  for (int st = 0; st < nst; ++st) {
-    const int K = radii[st];
+  for (int k = 0; k < st.nstages; ++k) {
+    const int K = st.stage_radius[k];
     int64_t rows = 1;
     for (int t = 0; t < d - 1; ++t) rows *= 2 * K + 1;
-    if (st > 0 && rows > 4096) break;
+    if (k > 0 && rows > 4096) break;
     p.stageK[p.nstages] = K;
-    p.stageGroup[p.nstages] = groups[st];
+    p.stageGroup[p.nstages] = st.stage_group[k];
     p.stageMode[p.nstages] = p16_ok(K, p.wc) ? kModeP16 : kModeI64;
     ++p.nstages;
   }
   p.ring_cap = kRingCostCap;
-  if (const char *env = std::getenv("DPC_RING_CAP")) {  // tuning override
-    const int v = std::atoi(env);
+  {
+    const int v = pick(opt ? opt->ring_cap : 0, env.ring_cap);
     if (v >= 1 && v <= 1 << 20) p.ring_cap = v;
   }
   p.nsx = int32_t((nc + p.wc - 1) / p.wc);
@@ -247,7 +289,7 @@ dpc_status check_common(const int32_t *pts, int64_t n, int32_t d, double d_cut, 
   if (n < 1 || n >= DPC_MAX_POINTS) return fail(DPC_EINVAL, "n must be in [1, 2^27)");
   if (d < 1 || d > DPC_MAX_DIM) return fail(DPC_EINVAL, "d must be in [1, 8]");
   if (!std::isfinite(d_cut) || !(d_cut > 0.0)) return fail(DPC_EINVAL, "d_cut must be finite and > 0");
-  if (!make_plan(n, d, d_cut, p)) return fail(DPC_EINVAL, "no plan for these sizes");
+  if (!make_plan(n, d, d_cut, nullptr, p)) return fail(DPC_EINVAL, "no plan for these sizes");
   if (ws_bytes < p->total) return fail(DPC_EWORKSPACE, "workspace smaller than dpc_workspace_bytes()");
   return DPC_OK;
 }
@@ -310,6 +352,93 @@ dpc_status run_dependent(const Plan &p, const Ws &w, const int32_t *pts, const i
   return DPC_OK;
 }
 
+void fill_plan_info(const Plan &p, dpc_plan_info *out) {
+  out->R = p.R;
+  out->cell_side = p.L;
+  out->cells_per_dim = p.nc;
+  out->cells = p.ncells;
+  out->strip_cells = p.wc;
+  out->strips = p.nstrips;
+  out->max_tasks = p.max_tasks;
+  out->mode = p.mode;
+  out->workspace_bytes = int64_t(p.total);
+  out->window_radius = p.K0;
+  out->stages = p.nstages;
+}
+
+dpc_status check_job(const dpc_job &j) {
+  if (!j.pts || !j.rho || !j.dep || !j.delta || !j.label || !j.ncenters) return fail(DPC_EINVAL, "null pointer");
+  if (j.n < 1 || j.n >= DPC_MAX_POINTS) return fail(DPC_EINVAL, "n must be in [1, 2^27)");
+  if (j.d < 1 || j.d > DPC_MAX_DIM) return fail(DPC_EINVAL, "d must be in [1, 8]");
+  if (!std::isfinite(j.d_cut) || !(j.d_cut > 0.0)) return fail(DPC_EINVAL, "d_cut must be finite and > 0");
+  if (j.rho_min < 0) return fail(DPC_EINVAL, "rho_min must be >= 0");
+  if (std::isnan(j.delta_min) || !(j.delta_min > j.d_cut)) return fail(DPC_EINVAL, "delta_min must exceed d_cut");
+  return DPC_OK;
+}
+
+// Gathers every job's device status word (sorted job order).
+__global__ void k_batch_status(const JobDev *jobs, int32_t njobs, uint32_t *out) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < njobs; k += int64_t(gridDim.x) * blockDim.x)
+    out[k] = jobs[k].w.hdr->status;
+}
+
+}  // namespace
+}  // namespace dpc
+
+// Host-side plan of a many-job launch.
+struct dpc_batch {
+  struct Map {
+    std::vector<uint32_t> vjob, vfirst, vcount;
+  };
+  int32_t njobs = 0;
+  std::vector<int32_t> order;   // order[k]: caller index of the k-th job (launch order)
+  std::vector<int32_t> pos;     // pos[i]: launch position of caller job i
+  std::vector<dpc_job> jobs;    // caller order
+  std::vector<dpc::Plan> plans; // caller order
+  std::vector<size_t> ws_off;   // launch order: offset of each job's workspace
+  Map maps[5];                  // one, pts, cells, strips, work
+  size_t o_status = 0, o_jobs = 0, o_map[5][3] = {}, total = 0;
+  int32_t ngroups = 0, gdim[DPC_MAX_DIM] = {}, max_stages = 0;
+  uint32_t gwork0[DPC_MAX_DIM] = {}, gwork1[DPC_MAX_DIM] = {};
+  void *bound = nullptr;
+};
+
+namespace dpc {
+namespace {
+
+enum { kMapOne = 0, kMapPts, kMapCells, kMapStrips, kMapWork };
+
+void add_blocks(dpc_batch::Map &m, uint32_t k, int64_t count) {
+  const uint32_t c = uint32_t(std::max<int64_t>(1, std::min<int64_t>(count, 1 << 20)));
+  m.vfirst.push_back(uint32_t(m.vjob.size()));
+  m.vcount.push_back(c);
+  m.vjob.insert(m.vjob.end(), c, k);
+}
+
+BatchMaps batch_maps(const dpc_batch &b, void *ws) {
+  char *base = static_cast<char *>(ws);
+  BatchMaps B;
+  std::memset(&B, 0, sizeof(B));
+  B.jobs = reinterpret_cast<const JobDev *>(base + b.o_jobs);
+  B.njobs = b.njobs;
+  VMap *vm[5] = {&B.one, &B.pts, &B.cells, &B.strips, &B.work};
+  for (int m = 0; m < 5; ++m) {
+    vm[m]->vjob = reinterpret_cast<const uint32_t *>(base + b.o_map[m][0]);
+    vm[m]->vfirst = reinterpret_cast<const uint32_t *>(base + b.o_map[m][1]);
+    vm[m]->vcount = reinterpret_cast<const uint32_t *>(base + b.o_map[m][2]);
+    vm[m]->v0 = 0;
+    vm[m]->v1 = uint32_t(b.maps[m].vjob.size());
+  }
+  B.ngroups = b.ngroups;
+  for (int g = 0; g < b.ngroups; ++g) {
+    B.gdim[g] = b.gdim[g];
+    B.gwork0[g] = b.gwork0[g];
+    B.gwork1[g] = b.gwork1[g];
+  }
+  B.max_stages = b.max_stages;
+  return B;
+}
+
 }  // namespace
 }  // namespace dpc
 
@@ -325,26 +454,181 @@ int64_t dpc_cutoff_square(double d_cut) { return cutoff_square(d_cut); }
 
 size_t dpc_workspace_bytes(int64_t n, int32_t d, double d_cut) {
   Plan p;
-  return make_plan(n, d, d_cut, &p) ? p.total : 0;
+  return make_plan(n, d, d_cut, nullptr, &p) ? p.total : 0;
 }
 
 dpc_status dpc_plan(int64_t n, int32_t d, double d_cut, dpc_plan_info *out) {
+  return dpc_plan_tuned(n, d, d_cut, nullptr, out);
+}
+
+dpc_status dpc_plan_tuned(int64_t n, int32_t d, double d_cut, const dpc_tuning *tuning, dpc_plan_info *out) {
   Plan p;
   if (!out) return fail(DPC_EINVAL, "null pointer argument");
-  if (!make_plan(n, d, d_cut, &p)) return fail(DPC_EINVAL, "no plan for these sizes");
-  out->R = p.R;
-  out->cell_side = p.L;
-  out->cells_per_dim = p.nc;
-  out->cells = p.ncells;
-  out->strip_cells = p.wc;
-  out->strips = p.nstrips;
-  out->max_tasks = p.max_tasks;
-  out->mode = p.mode;
-  out->workspace_bytes = int64_t(p.total);
-  out->window_radius = p.K0;
-  out->stages = p.nstages;
+  if (!make_plan(n, d, d_cut, tuning, &p)) return fail(DPC_EINVAL, "no plan for these sizes or options");
+  fill_plan_info(p, out);
   return DPC_OK;
 }
+
+dpc_status dpc_batch_plan(const dpc_job *jobs, int32_t njobs, const dpc_tuning *tuning, dpc_batch **out,
+                          size_t *ws_bytes) {
+  if (!jobs || !out || !ws_bytes || njobs < 1) return fail(DPC_EINVAL, "null pointer argument or no jobs");
+  *out = nullptr;
+  dpc_batch *b = new dpc_batch;
+  b->njobs = njobs;
+  b->jobs.assign(jobs, jobs + njobs);
+  b->plans.resize(njobs);
+  for (int32_t i = 0; i < njobs; ++i) {
+    dpc_status st = check_job(jobs[i]);
+    if (st == DPC_OK && !make_plan(jobs[i].n, jobs[i].d, jobs[i].d_cut, tuning ? tuning + i : nullptr, &b->plans[i]))
+      st = fail(DPC_EINVAL, "no plan for these sizes or options");
+    if (st != DPC_OK) {
+      g_last_error = "job " + std::to_string(i) + ": " + g_last_error;
+      delete b;
+      return st;
+    }
+  }
+  // Launch order: by dimension (one launch per dimension for the templated
+  // kernels), then largest first so the long jobs start early.
+  b->order.resize(njobs);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int32_t x, int32_t y) {
+    if (jobs[x].d != jobs[y].d) return jobs[x].d < jobs[y].d;
+    return jobs[x].n > jobs[y].n;
+  });
+  b->pos.resize(njobs);
+  for (int32_t k = 0; k < njobs; ++k) b->pos[b->order[k]] = k;
+  for (int32_t k = 0; k < njobs; ++k) {
+    const Plan &p = b->plans[b->order[k]];
+    add_blocks(b->maps[kMapOne], uint32_t(k), 1);
+    add_blocks(b->maps[kMapPts], uint32_t(k), (p.n + kBatchPoints - 1) / kBatchPoints);
+    add_blocks(b->maps[kMapCells], uint32_t(k), (p.ncells + kBatchCells) / kBatchCells);
+    add_blocks(b->maps[kMapStrips], uint32_t(k), (p.nstrips + kBatchPoints) / kBatchPoints);
+    const uint32_t w0 = uint32_t(b->maps[kMapWork].vjob.size());
+    add_blocks(b->maps[kMapWork], uint32_t(k), std::min<int64_t>(2048, (p.max_tasks + kBatchTasks - 1) / kBatchTasks));
+    if (b->ngroups == 0 || b->gdim[b->ngroups - 1] != p.d) {
+      b->gdim[b->ngroups] = p.d;
+      b->gwork0[b->ngroups] = w0;
+      ++b->ngroups;
+    }
+    b->gwork1[b->ngroups - 1] = uint32_t(b->maps[kMapWork].vjob.size());
+    b->max_stages = std::max(b->max_stages, p.nstages);
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  b->o_status = take(size_t(njobs) * 4);
+  b->o_jobs = take(size_t(njobs) * sizeof(JobDev));
+  for (int m = 0; m < 5; ++m) {
+    b->o_map[m][0] = take(b->maps[m].vjob.size() * 4);
+    b->o_map[m][1] = take(b->maps[m].vfirst.size() * 4);
+    b->o_map[m][2] = take(b->maps[m].vcount.size() * 4);
+  }
+  b->ws_off.resize(njobs);
+  for (int32_t k = 0; k < njobs; ++k) b->ws_off[k] = take(b->plans[b->order[k]].total);
+  b->total = o;
+  *ws_bytes = o;
+  *out = b;
+  return DPC_OK;
+}
+
+dpc_status dpc_batch_bind(dpc_batch *b, void *ws, size_t ws_bytes) {
+  if (!b || !ws) return fail(DPC_EINVAL, "null pointer argument");
+  if (ws_bytes < b->total) return fail(DPC_EWORKSPACE, "workspace smaller than the batch needs");
+  char *base = static_cast<char *>(ws);
+  const size_t head = b->ws_off.empty() ? b->total : b->ws_off[0];
+  std::vector<char> host(head, 0);
+  JobDev *jd = reinterpret_cast<JobDev *>(host.data() + b->o_jobs);
+  for (int32_t k = 0; k < b->njobs; ++k) {
+    const int32_t i = b->order[k];
+    const dpc_job &j = b->jobs[i];
+    JobDev &J = jd[k];
+    std::memset(&J, 0, sizeof(J));
+    J.p = b->plans[i];
+    J.w = resolve(J.p, base + b->ws_off[k]);
+    J.pts = j.pts;
+    J.rho = j.rho;
+    J.dep = j.dep;
+    J.delta = j.delta;
+    J.label = j.label;
+    J.ncenters = j.ncenters;
+    J.rho_min = j.rho_min;
+    J.delta_min = j.delta_min;
+  }
+  for (int m = 0; m < 5; ++m) {
+    const auto &M = b->maps[m];
+    std::memcpy(host.data() + b->o_map[m][0], M.vjob.data(), M.vjob.size() * 4);
+    std::memcpy(host.data() + b->o_map[m][1], M.vfirst.data(), M.vfirst.size() * 4);
+    std::memcpy(host.data() + b->o_map[m][2], M.vcount.data(), M.vcount.size() * 4);
+  }
+  hipError_t e = hipMemcpy(base, host.data(), head, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return device_fail(e, "batch table upload");
+  b->bound = ws;
+  return DPC_OK;
+}
+
+dpc_status dpc_batch_run(const dpc_batch *b, void *ws, void *stream) {
+  if (!b || !ws) return fail(DPC_EINVAL, "null pointer argument");
+  if (b->bound != ws) return fail(DPC_EINVAL, "workspace not bound to this batch (dpc_batch_bind)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const BatchMaps B = batch_maps(*b, ws);
+  hipError_t e;
+  if ((e = batch_start(B, s)) != hipSuccess) return device_fail(e, "batch start");
+  {
+    ProfScope ps(s, kProfGrid);
+    if ((e = batch_build_grid(B, s)) != hipSuccess) return device_fail(e, "batch grid build");
+  }
+  {
+    ProfScope ps(s, kProfDensity);
+    if ((e = batch_density(B, s)) != hipSuccess) return device_fail(e, "batch density");
+  }
+  {
+    ProfScope ps(s, kProfRankSort);
+    if ((e = batch_rank(B, s)) != hipSuccess) return device_fail(e, "batch rank");
+  }
+  if ((e = batch_dependent(B, s)) != hipSuccess) return device_fail(e, "batch dependent");
+  ProfScope ps(s, kProfLabel);
+  if ((e = batch_label(B, s)) != hipSuccess) return device_fail(e, "batch label");
+  return DPC_OK;
+}
+
+dpc_status dpc_batch_sync_status(const dpc_batch *b, void *ws, void *stream, int32_t *first_bad) {
+  if (!b || !ws) return fail(DPC_EINVAL, "null pointer argument");
+  if (first_bad) *first_bad = -1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(ws);
+  uint32_t *dst = reinterpret_cast<uint32_t *>(base + b->o_status);
+  DPC_LAUNCH((k_batch_status), blocks_for(b->njobs, kBlock), kBlock, s,
+             reinterpret_cast<const JobDev *>(base + b->o_jobs), b->njobs, dst);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return device_fail(e, "stream synchronize");
+  std::vector<uint32_t> st(b->njobs);
+  e = hipMemcpy(st.data(), dst, st.size() * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return device_fail(e, "status read");
+  uint32_t all = 0;
+  int32_t bad = -1;
+  for (int32_t i = 0; i < b->njobs; ++i) {
+    const uint32_t v = st[b->pos[i]];
+    all |= v;
+    if (v && bad < 0) bad = i;
+  }
+  if (first_bad) *first_bad = bad;
+  if (all & 1u) return fail(DPC_ERANGE, "a coordinate was outside [0, 2^17) and was clamped");
+  if (all & 2u) return fail(DPC_EINVAL, "inconsistent rho or dep input (clamped or cut)");
+  g_last_error.clear();
+  return DPC_OK;
+}
+
+dpc_status dpc_batch_job_plan(const dpc_batch *b, int32_t i, dpc_plan_info *out) {
+  if (!b || !out) return fail(DPC_EINVAL, "null pointer argument");
+  if (i < 0 || i >= b->njobs) return fail(DPC_EINVAL, "job index out of range");
+  fill_plan_info(b->plans[i], out);
+  return DPC_OK;
+}
+
+void dpc_batch_free(dpc_batch *b) { delete b; }
 
 dpc_status dpc_density(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32_t *rho, void *ws,
                        size_t ws_bytes, void *stream) {

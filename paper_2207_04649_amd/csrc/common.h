@@ -21,6 +21,9 @@ constexpr uint64_t kIdMask = (uint64_t(1) << kIdBits) - 1;
 constexpr uint64_t kNoKey = ~uint64_t(0);
 constexpr int kScanItems = 16;           // items per thread in the block scan
 constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kBatchPoints = 4096;       // points (or strips) per virtual block of a many-job launch
+constexpr int kBatchCells = 8192;        // table cells per virtual block of a many-job launch
+constexpr int kBatchTasks = 8;           // tasks per virtual block of the persistent kernels
 constexpr int kPeakChunk = 256;          // rank-order candidates per prefix-scan work unit
 constexpr int kRingCostCap = 48;         // default of Plan::ring_cap
 
@@ -113,6 +116,50 @@ inline Ws resolve(const Plan &p, void *base) {
   return w;
 }
 
+// One job of a many-job launch, as the kernels read it (device memory).
+struct JobDev {
+  Plan p;
+  Ws w;
+  const int32_t *pts;
+  int32_t *rho, *dep;
+  double *delta;
+  int32_t *label;
+  int64_t *ncenters;
+  int32_t rho_min, pad;
+  double delta_min;
+};
+
+// Virtual blocks of a many-job launch: vjob[v] is the job of virtual block v,
+// and job j owns the vcount[j] virtual blocks from vfirst[j].  A launch covers
+// virtual blocks [v0, v1) (jobs of one dimension for the templated kernels).
+struct VMap {
+  const uint32_t *vjob, *vfirst, *vcount;
+  uint32_t v0, v1;
+};
+
+// Host description of a many-job launch: the device job table and the virtual
+// block maps of each kind of phase.  Jobs are ordered by dimension, so the jobs
+// of one dimension own one contiguous range of every map.
+struct BatchMaps {
+  const JobDev *jobs;
+  int32_t njobs;
+  VMap one;     // one virtual block per job
+  VMap pts;     // about kBatchPoints points per virtual block
+  VMap cells;   // about kBatchCells table cells per virtual block
+  VMap strips;  // about kBatchPoints strips per virtual block
+  VMap work;    // persistent kernels: about kBatchTasks tasks per virtual block
+  int32_t ngroups;
+  int32_t gdim[DPC_MAX_DIM];                       // dimension of each group
+  uint32_t gwork0[DPC_MAX_DIM], gwork1[DPC_MAX_DIM];  // its work virtual blocks
+  int32_t max_stages;
+};
+
+// Blocks of a many-job launch over m (0: nothing to launch).
+inline unsigned vgrid(const VMap &m) {
+  const uint32_t v = m.v1 > m.v0 ? m.v1 - m.v0 : 0u;
+  return v < 2048u ? v : 2048u;
+}
+
 // Host-side launch helpers (implemented in the .hip files).
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_scan(uint32_t *data, int64_t count, uint32_t *bsum, hipStream_t s);
@@ -125,6 +172,13 @@ hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const
                         int32_t rho_min, double delta_min, int32_t *label, int64_t *ncenters,
                         DevHeader *hdr, hipStream_t s);
 hipError_t reset_counters(DevHeader *hdr, bool grid, hipStream_t s);
+// Many-job launches (every phase for all jobs of a BatchMaps, one launch each).
+hipError_t batch_start(const BatchMaps &B, hipStream_t s);
+hipError_t batch_build_grid(const BatchMaps &B, hipStream_t s);
+hipError_t batch_density(const BatchMaps &B, hipStream_t s);
+hipError_t batch_rank(const BatchMaps &B, hipStream_t s);
+hipError_t batch_dependent(const BatchMaps &B, hipStream_t s);
+hipError_t batch_label(const BatchMaps &B, hipStream_t s);
 hipError_t clear_status(DevHeader *hdr, hipStream_t s);
 unsigned persistent_blocks(int64_t max_waves);
 
@@ -212,20 +266,26 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool take) {
   return atomicAdd(counter, take ? 1u : 0u);
 }
 
-// Index of the calling wave in the grid, and the number of waves: persistent
-// kernels take items wave_index(), wave_index() + grid_waves(), ...  A static
+// A job's share of a launch: block b of nb blocks.  For a single-job call it
+// is the whole grid; in a many-job launch each job gets a run of virtual blocks
+// that the launch's blocks take in turn.  Kernels are written against Blk, so
+// both kinds of launch run the same code.
+struct Blk {
+  uint32_t b, nb;
+};
+
+__device__ __forceinline__ Blk grid_blk() { return Blk{blockIdx.x, gridDim.x}; }
+
+// Index of the calling wave among the job's waves, and their number: persistent
+// loops take items wave_index(k), wave_index(k) + grid_waves(k), ...  A static
 // interleave needs no shared counter; one returning atomic per work item on a
 // single address serialises in L2 and delays the whole grid.
-__device__ __forceinline__ uint32_t wave_index() {
-  return uniform(uint32_t(blockIdx.x * dpc::kWavesPerBlock + threadIdx.x / dpc::kWave));
+__device__ __forceinline__ uint32_t wave_index(Blk k) {
+  return uniform(uint32_t(k.b * dpc::kWavesPerBlock + threadIdx.x / dpc::kWave));
 }
-__device__ __forceinline__ uint32_t grid_waves() { return uint32_t(gridDim.x * dpc::kWavesPerBlock); }
-
-// Next work item of the whole wave (all 64 lanes active).
-__device__ __forceinline__ uint32_t wave_next(uint32_t *counter) {
-  const uint32_t t = atomicAdd(counter, lane_id() == 0 ? 1u : 0u);
-  return uniform(t);
-}
+__device__ __forceinline__ uint32_t grid_waves(Blk k) { return k.nb * uint32_t(dpc::kWavesPerBlock); }
+__device__ __forceinline__ int64_t thread_index(Blk k) { return int64_t(k.b) * dpc::kBlock + threadIdx.x; }
+__device__ __forceinline__ int64_t grid_threads(Blk k) { return int64_t(k.nb) * dpc::kBlock; }
 
 // a - b on two packed signed 16-bit halves (wrapping), as a 32-bit word.
 __device__ __forceinline__ uint32_t pk_sub16(uint32_t a, uint32_t b) {
@@ -257,3 +317,25 @@ __device__ __forceinline__ int32_t dot2_self_v(uint32_t a, int32_t acc) {
 }
 __device__ __forceinline__ int32_t dot2_self_s(uint32_t a, int32_t acc) { return dot2_self_v(a, acc); }
 #endif
+
+// Copy of a read-only struct through the constant address space: with a
+// wave-uniform address its words become scalar loads, and words that are never
+// used are never loaded.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *src) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+  T out;
+  uint32_t *o = reinterpret_cast<uint32_t *>(&out);
+  DPC_CONST(uint32_t) *s = as_const(reinterpret_cast<const uint32_t *>(src));
+#pragma unroll
+  for (int i = 0; i < int(sizeof(T) / 4); ++i) o[i] = s[i];
+  return out;
+}
+
+// Job and block coordinates of virtual block v of a many-job launch.
+__device__ __forceinline__ uint32_t vjob_of(const dpc::VMap &m, uint32_t v) {
+  return uniform(uint32_t(as_const(m.vjob)[v]));
+}
+__device__ __forceinline__ Blk vblk_of(const dpc::VMap &m, uint32_t v, uint32_t j) {
+  return Blk{v - uniform(uint32_t(as_const(m.vfirst)[j])), uniform(uint32_t(as_const(m.vcount)[j]))};
+}

@@ -14,7 +14,7 @@ namespace dpc {
 namespace {
 
 template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w, int32_t *__restrict__ rho) {
+__device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w, int32_t *__restrict__ rho) {
   constexpr int W = (D + 1) / 2;
   const int lane = lane_id();
   DPC_CONST(uint32_t) *spk = as_const(w.spk);
@@ -27,8 +27,8 @@ __global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w, int32_t *__res
   int nrow = 1;
   for (int t = 0; t < D - 1; ++t) nrow *= 2 * K + 1;
 
-  const uint32_t nw = grid_waves();
-  for (uint32_t t = wave_index(); t < ntasks; t += nw) {
+  const uint32_t nw = grid_waves(blk);
+  for (uint32_t t = wave_index(blk); t < ntasks; t += nw) {
     const uint32_t qb = uniform(uint32_t(tc[4 * int64_t(t)]));
     const uint32_t qe = uniform(uint32_t(tc[4 * int64_t(t) + 1]));
     TaskGeom<D> g;
@@ -94,6 +94,27 @@ __global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w, int32_t *__res
   }
 }
 
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w, int32_t *__restrict__ rho) {
+  density_body<D, MODE>(grid_blk(), p, w, rho);
+}
+
+// Many-job form: the jobs of one dimension, each on its own virtual blocks.
+template <int D>
+__global__ __launch_bounds__(kBlock) void kb_density(const JobDev *jobs, VMap m) {
+  for (uint32_t v = m.v0 + blockIdx.x; v < m.v1; v += gridDim.x) {
+    const uint32_t j = vjob_of(m, v);
+    const Blk k = vblk_of(m, v, j);
+    const Plan p = load_uniform(&jobs[j].p);
+    const Ws w = load_uniform(&jobs[j].w);
+    int32_t *rho = as_const(jobs)[j].rho;
+    if (p.mode == kModeP16)
+      density_body<D, kModeP16>(k, p, w, rho);
+    else
+      density_body<D, kModeI64>(k, p, w, rho);
+  }
+}
+
 template <int D>
 hipError_t launch_d(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s, unsigned blocks) {
   if (p.mode == kModeP16)
@@ -126,6 +147,27 @@ hipError_t launch_density(const Plan &p, const Ws &w, int32_t *rho, hipStream_t 
     case 8: return launch_d<8>(p, w, rho, s, blocks);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t batch_density(const BatchMaps &B, hipStream_t s) {
+  for (int g = 0; g < B.ngroups; ++g) {
+    VMap m = B.work;
+    m.v0 = B.gwork0[g];
+    m.v1 = B.gwork1[g];
+    if (!vgrid(m)) continue;
+    switch (B.gdim[g]) {
+      case 1: DPC_LAUNCH((kb_density<1>), vgrid(m), kBlock, s, B.jobs, m); break;
+      case 2: DPC_LAUNCH((kb_density<2>), vgrid(m), kBlock, s, B.jobs, m); break;
+      case 3: DPC_LAUNCH((kb_density<3>), vgrid(m), kBlock, s, B.jobs, m); break;
+      case 4: DPC_LAUNCH((kb_density<4>), vgrid(m), kBlock, s, B.jobs, m); break;
+      case 5: DPC_LAUNCH((kb_density<5>), vgrid(m), kBlock, s, B.jobs, m); break;
+      case 6: DPC_LAUNCH((kb_density<6>), vgrid(m), kBlock, s, B.jobs, m); break;
+      case 7: DPC_LAUNCH((kb_density<7>), vgrid(m), kBlock, s, B.jobs, m); break;
+      case 8: DPC_LAUNCH((kb_density<8>), vgrid(m), kBlock, s, B.jobs, m); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
 }
 
 }  // namespace dpc

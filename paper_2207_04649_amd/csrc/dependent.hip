@@ -128,7 +128,7 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int K, 
 // open points (all points in the first stage) into batches of 64 per strip
 // through an LDS queue, and searches each batch's window of radius K.
 template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_search(Plan p, Ws w, int K, int group, int first) {
+__device__ __forceinline__ void search_body(Blk blk, const Plan &p, const Ws &w, int K, int group, int first) {
   __shared__ uint32_t queue_all[kWavesPerBlock][2 * kWave + 1];  // + a spare slot
   uint32_t *queue = queue_all[threadIdx.x / kWave];
   const int lane = lane_id();
@@ -137,8 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_search(Plan p, Ws w, int K, int grou
   const uint32_t ngroups = (ntasks + uint32_t(group) - 1) / uint32_t(group);
   const uint64_t below = (uint64_t(1) << lane) - 1;
 
-  const uint32_t nw = grid_waves();
-  for (uint32_t gi = wave_index(); gi < ngroups; gi += nw) {
+  const uint32_t nw = grid_waves(blk);
+  for (uint32_t gi = wave_index(blk); gi < ngroups; gi += nw) {
     uint32_t pending = 0, cur = 0;
     const uint32_t t_end = min((gi + 1) * uint32_t(group), ntasks);
     for (uint32_t t = gi * uint32_t(group); t < t_end; ++t) {
@@ -179,33 +179,38 @@ __global__ __launch_bounds__(kBlock) void k_search(Plan p, Ws w, int K, int grou
 // counter that every wave bumps serialises in L2).
 constexpr int kCollectPer = 16;
 
-__global__ __launch_bounds__(kBlock) void k_collect(Plan p, const uint8_t *__restrict__ flag,
-                                                    uint32_t *__restrict__ unres, DevHeader *__restrict__ hdr) {
+__device__ __forceinline__ void collect_body(Blk blk, const Plan &p, const uint8_t *__restrict__ flag,
+                                             uint32_t *__restrict__ unres, DevHeader *__restrict__ hdr) {
   __shared__ uint32_t wave_tot[kWavesPerBlock];
   __shared__ uint32_t base;
-  const int64_t i0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * kCollectPer;
-  uint32_t open = 0;
+  constexpr int64_t kChunk = int64_t(kBlock) * kCollectPer;
+  const int64_t chunks = (p.n + kChunk - 1) / kChunk;
+  for (int64_t c = blk.b; c < chunks; c += blk.nb) {
+    const int64_t i0 = c * kChunk + int64_t(threadIdx.x) * kCollectPer;
+    uint32_t open = 0;
 #pragma unroll
-  for (int k = 0; k < kCollectPer; ++k) {
-    const int64_t i = i0 + k;
-    open |= (i < p.n && flag[i < p.n ? i : 0] != 0) ? (1u << k) : 0u;
-  }
-  uint32_t tot;
-  const uint32_t off = wave_exclusive_scan(uint32_t(__popc(open)), &tot);
-  const int wv = threadIdx.x / kWave;
-  wave_tot[wv] = tot;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t sum = 0;
-    for (int k = 0; k < kWavesPerBlock; ++k) sum += wave_tot[k];
-    base = atomicAdd(&hdr->n_unres, sum);
-  }
-  __syncthreads();
-  uint32_t at = base + off;
-  for (int k = 0; k < wv; ++k) at += wave_tot[k];
+    for (int k = 0; k < kCollectPer; ++k) {
+      const int64_t i = i0 + k;
+      open |= (i < p.n && flag[i < p.n ? i : 0] != 0) ? (1u << k) : 0u;
+    }
+    uint32_t tot;
+    const uint32_t off = wave_exclusive_scan(uint32_t(__popc(open)), &tot);
+    const int wv = threadIdx.x / kWave;
+    wave_tot[wv] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t sum = 0;
+      for (int k = 0; k < kWavesPerBlock; ++k) sum += wave_tot[k];
+      base = atomicAdd(&hdr->n_unres, sum);
+    }
+    __syncthreads();
+    uint32_t at = base + off;
+    for (int k = 0; k < wv; ++k) at += wave_tot[k];
 #pragma unroll
-  for (int k = 0; k < kCollectPer; ++k) {
-    if (open & (1u << k)) unres[at++] = uint32_t(i0 + k);
+    for (int k = 0; k < kCollectPer; ++k) {
+      if (open & (1u << k)) unres[at++] = uint32_t(i0 + k);
+    }
+    __syncthreads();
   }
 }
 
@@ -254,7 +259,7 @@ __device__ __forceinline__ uint64_t exact_d2_v(const int32_t *a, const int32_t *
 // closer than the exterior of the block; it goes to the prefix scan when the
 // passes have cost more than that scan would.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w, int k_start) {
+__device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, int k_start) {
   __shared__ SegLds lds_all[kWavesPerBlock];
   SegLds &lds = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
@@ -264,8 +269,8 @@ __global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w, int k_start) {
   DPC_CONST(uint32_t) *unres = as_const(w.unres);
   DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
 
-  const uint32_t nw = grid_waves();
-  for (uint32_t u = wave_index(); u < nunres; u += nw) {
+  const uint32_t nw = grid_waves(blk);
+  for (uint32_t u = wave_index(blk); u < nunres; u += nw) {
     const uint32_t q = uniform(unres[u]);
     int32_t x[D], c[D];
 #pragma unroll
@@ -419,7 +424,7 @@ __device__ __forceinline__ void peak_batch_load(DPC_CONST(int32_t) * rpc, DPC_CO
 }
 
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
+__device__ __forceinline__ void peaks_body(Blk blk, const Plan &p, const Ws &w) {
   constexpr int B = 16 / D > 0 ? 16 / D : 1;  // candidates per scalar-load batch
   const int lane = lane_id();
   const uint32_t npeaks = uniform(as_const(&w.hdr->n_peaks)[0]);
@@ -429,8 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
   DPC_CONST(int32_t) *rpc = as_const(w.rpts);
   DPC_CONST(int32_t) *ridc = as_const(w.rid);
 
-  const uint32_t nw = grid_waves();
-  for (uint64_t u = wave_index(); u < units; u += nw) {
+  const uint32_t nw = grid_waves(blk);
+  for (uint64_t u = wave_index(blk); u < units; u += nw) {
     const uint32_t g = uint32_t(u % ngroups);
     const uint32_t ch = uint32_t(u / ngroups);
     const uint32_t q = w.peaks[min(g * uint32_t(kWave) + uint32_t(lane), npeaks - 1u)];
@@ -492,19 +497,92 @@ __global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
 
 // -------------------------------------------------------------------- finish
 
-__global__ void k_finish(Plan p, const uint64_t *__restrict__ best, int32_t *__restrict__ dep,
-                         double *__restrict__ delta) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  const uint64_t key = best[i];
-  if (key == kNoKey) {
-    dep[i] = -1;
-    delta[i] = __builtin_huge_val();
-  } else {
-    dep[i] = int32_t(key & kIdMask);
-    delta[i] = __builtin_sqrt(double(key >> kIdBits));  // correctly rounded (IEEE sqrt)
+__device__ __forceinline__ void finish_body(Blk blk, const Plan &p, const uint64_t *__restrict__ best,
+                                            int32_t *__restrict__ dep, double *__restrict__ delta) {
+  for (int64_t i = thread_index(blk); i < p.n; i += grid_threads(blk)) {
+    const uint64_t key = best[i];
+    if (key == kNoKey) {
+      dep[i] = -1;
+      delta[i] = __builtin_huge_val();
+    } else {
+      dep[i] = int32_t(key & kIdMask);
+      delta[i] = __builtin_sqrt(double(key >> kIdBits));  // correctly rounded (IEEE sqrt)
+    }
   }
 }
+
+// -------------------------------------------------------------------- kernels
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_search(Plan p, Ws w, int K, int group, int first) {
+  search_body<D, MODE>(grid_blk(), p, w, K, group, first);
+}
+__global__ __launch_bounds__(kBlock) void k_collect(Plan p, Ws w) { collect_body(grid_blk(), p, w.flag, w.unres, w.hdr); }
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w, int k_start) {
+  ringk_body<D>(grid_blk(), p, w, k_start);
+}
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
+  peaks_body<D>(grid_blk(), p, w);
+}
+__global__ __launch_bounds__(kBlock) void k_finish(Plan p, Ws w, int32_t *dep, double *delta) {
+  finish_body(grid_blk(), p, w.best, dep, delta);
+}
+
+// Many-job forms: virtual block v of map m runs the body for its job.
+#define DPC_FOR_VBLOCKS(m)                                             \
+  for (uint32_t v = (m).v0 + blockIdx.x; v < (m).v1; v += gridDim.x) { \
+    const uint32_t j = vjob_of((m), v);                                \
+    const Blk k = vblk_of((m), v, j);                                  \
+    const Plan p = load_uniform(&jobs[j].p);                                \
+    const Ws w = load_uniform(&jobs[j].w);
+
+// Stage st of every job that has one (the mode is per job).
+template <int D>
+__global__ __launch_bounds__(kBlock) void kb_search(const JobDev *jobs, VMap m, int st) {
+  DPC_FOR_VBLOCKS(m)
+  if (st < p.nstages) {
+    // stage parameters straight from the job table (scalar loads; indexing the
+    // local copy with a run-time stage would put it in scratch memory)
+    const int K = uniform(int32_t(as_const(jobs)[j].p.stageK[st]));
+    const int group = uniform(int32_t(as_const(jobs)[j].p.stageGroup[st]));
+    const int mode = uniform(int32_t(as_const(jobs)[j].p.stageMode[st]));
+    if (mode == kModeP16)
+      search_body<D, kModeP16>(k, p, w, K, group, st == 0 ? 1 : 0);
+    else
+      search_body<D, kModeI64>(k, p, w, K, group, st == 0 ? 1 : 0);
+  }
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_collect(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  collect_body(k, p, w.flag, w.unres, w.hdr);
+}
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void kb_ringk(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  ringk_body<D>(k, p, w, uniform(int32_t(as_const(jobs)[j].p.stageK[p.nstages - 1])));
+}
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void kb_peaks(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  peaks_body<D>(k, p, w);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_finish(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  finish_body(k, p, w.best, as_const(jobs)[j].dep, as_const(jobs)[j].delta);
+}
+}
+
+#undef DPC_FOR_VBLOCKS
 
 template <int D>
 hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta, hipStream_t s) {
@@ -522,7 +600,7 @@ hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta,
   const unsigned rb = persistent_blocks(p.n);
   {
     ProfScope ps(s, kProfRingK);
-    DPC_LAUNCH((k_collect), blocks_for(p.n, kBlock * kCollectPer), kBlock, s, p, w.flag, w.unres, w.hdr);
+    DPC_LAUNCH((k_collect), blocks_for(p.n, kBlock * kCollectPer), kBlock, s, p, w);
     DPC_LAUNCH((k_ringk<D>), rb, kBlock, s, p, w, p.stageK[p.nstages - 1]);
   }
   {
@@ -530,7 +608,7 @@ hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta,
     DPC_LAUNCH((k_peaks<D>), rb, kBlock, s, p, w);
   }
   ProfScope ps(s, kProfFinish);
-  DPC_LAUNCH((k_finish), blocks_for(p.n, kBlock), kBlock, s, p, w.best, dep, delta);
+  DPC_LAUNCH((k_finish), blocks_for(p.n, kBlock), kBlock, s, p, w, dep, delta);
   return hipGetLastError();
 }
 
@@ -548,6 +626,46 @@ hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *de
     case 8: return launch_dep_d<8>(p, w, dep, delta, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Stages, ring search and prefix scan of every dimension group, then finish.
+// The open-point lists are collected for all jobs after the stages of every
+// group have run, so the groups' stages go first.
+hipError_t batch_dependent(const BatchMaps &B, hipStream_t s) {
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int g = 0; g < B.ngroups; ++g) {
+      VMap m = B.work;
+      m.v0 = B.gwork0[g];
+      m.v1 = B.gwork1[g];
+      if (!vgrid(m)) continue;
+      switch (B.gdim[g]) {
+#define DPC_GROUP(DD)                                                                               \
+  case DD:                                                                                          \
+    if (pass == 0) {                                                                                \
+      ProfScope ps(s, kProfSearch);                                                                 \
+      for (int st = 0; st < B.max_stages; ++st) DPC_LAUNCH((kb_search<DD>), vgrid(m), kBlock, s, B.jobs, m, st); \
+    } else {                                                                                        \
+      {                                                                                             \
+        ProfScope ps(s, kProfRingK);                                                                \
+        DPC_LAUNCH((kb_ringk<DD>), vgrid(m), kBlock, s, B.jobs, m);                                 \
+      }                                                                                             \
+      ProfScope ps(s, kProfPeaks);                                                                  \
+      DPC_LAUNCH((kb_peaks<DD>), vgrid(m), kBlock, s, B.jobs, m);                                   \
+    }                                                                                               \
+    break;
+        DPC_GROUP(1) DPC_GROUP(2) DPC_GROUP(3) DPC_GROUP(4) DPC_GROUP(5) DPC_GROUP(6) DPC_GROUP(7) DPC_GROUP(8)
+#undef DPC_GROUP
+        default: return hipErrorInvalidValue;
+      }
+    }
+    if (pass == 0 && vgrid(B.pts)) {
+      ProfScope ps(s, kProfRingK);
+      DPC_LAUNCH((kb_collect), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+    }
+  }
+  ProfScope ps(s, kProfFinish);
+  if (vgrid(B.pts)) DPC_LAUNCH((kb_finish), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  return hipGetLastError();
 }
 
 }  // namespace dpc

@@ -1,25 +1,27 @@
-// Grid construction (counting sort of points into d_cut-sized cells), the
-// density-rank sort, and the device-wide exclusive scan both use.
+// Grid construction (counting sort of points into cells), the density-rank
+// sort, and the exclusive scan both use.
 //
 // The cells replace the paper's kd-tree (Section 3) as the range-search index:
-// with cell side L >= floor(sqrt(R - 1)), R = ceil(d_cut^2), every point closer
-// than d_cut to p lies in the 3^d cells around p's cell (Def. 1).
+// with cell side L, every point closer than d_cut to p lies in the cells within
+// ceil(floor(sqrt(R - 1)) / L) cells of p's cell, R = ceil(d_cut^2) (Def. 1).
+//
+// Every kernel is a body over Blk (a job's share of the launch) with two
+// wrappers: k_* runs one job on the whole grid, kb_* runs the jobs of a
+// many-job launch, each virtual block calling the body for its job.
 #include "common.h"
 
 namespace dpc {
 namespace {
 
-__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t count) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (; i < count; i += stride) p[i] = v;
-}
+// ---- bodies ----
 
-// ---- exclusive scan of u32, three passes over tiles of kScanTile items ----
+__device__ __forceinline__ void fill_u32(Blk k, uint32_t *p, uint32_t v, int64_t count) {
+  for (int64_t i = thread_index(k); i < count; i += grid_threads(k)) p[i] = v;
+}
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total) {
   __shared__ uint32_t wsum[kBlock / kWave];
-  const int lane = lane_id(), wave = threadIdx.x / kWave;
+  const int wave = threadIdx.x / kWave;
   uint32_t wt;
   uint32_t x = wave_exclusive_scan(v, &wt);
   wsum[wave] = wt;  // every lane stores the same wave total
@@ -36,107 +38,114 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *t
   return x + before;
 }
 
-// Tile-local exclusive scan; writes each tile's total to bsum.
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *data, int64_t count, uint32_t *bsum) {
-  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t sum = 0;
+// Exclusive scan of u32 in three passes over tiles of kScanTile items:
+// tile-local scans with each tile's total written to bsum ...
+__device__ __forceinline__ void scan_tiles(Blk k, uint32_t *data, int64_t count, uint32_t *bsum) {
+  const int64_t tiles = (count + kScanTile - 1) / kScanTile;
+  for (int64_t t = k.b; t < tiles; t += k.nb) {
+    const int64_t base = t * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + k;
-    v[k] = i < count ? data[i] : 0u;
-    sum += v[k];
-  }
-  uint32_t total;
-  uint32_t run = block_exclusive_scan(sum, &total);
+    for (int j = 0; j < kScanItems; ++j) {
+      const int64_t i = base + j;
+      v[j] = i < count ? data[i] : 0u;
+      sum += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, &total);
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + k;
-    if (i < count) data[i] = run;
-    run += v[k];
+    for (int j = 0; j < kScanItems; ++j) {
+      const int64_t i = base + j;
+      if (i < count) data[i] = run;
+      run += v[j];
+    }
+    if (threadIdx.x == 0) bsum[t] = total;
   }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-// One workgroup scans the tile totals in place (any count, in rounds of kScanTile).
-__global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t *bsum, int64_t count) {
+// ... one workgroup scans the tile totals in place (in rounds of kScanTile) ...
+__device__ __forceinline__ void scan_sums(uint32_t *bsum, int64_t count) {
+  const int64_t tiles = (count + kScanTile - 1) / kScanTile;
   uint32_t carry = 0;
-  for (int64_t round = 0; round < count; round += kScanTile) {
+  for (int64_t round = 0; round < tiles; round += kScanTile) {
     const int64_t base = round + int64_t(threadIdx.x) * kScanItems;
     uint32_t v[kScanItems];
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      int64_t i = base + k;
-      v[k] = i < count ? bsum[i] : 0u;
-      sum += v[k];
+    for (int j = 0; j < kScanItems; ++j) {
+      const int64_t i = base + j;
+      v[j] = i < tiles ? bsum[i] : 0u;
+      sum += v[j];
     }
     uint32_t total;
     uint32_t run = block_exclusive_scan(sum, &total) + carry;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-      int64_t i = base + k;
-      if (i < count) bsum[i] = run;
-      run += v[k];
+    for (int j = 0; j < kScanItems; ++j) {
+      const int64_t i = base + j;
+      if (i < tiles) bsum[i] = run;
+      run += v[j];
     }
     carry += total;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *data, int64_t count, const uint32_t *bsum) {
-  const uint32_t add = bsum[blockIdx.x];
-  const int64_t base = int64_t(blockIdx.x) * kScanTile;
-  for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
-    int64_t i = base + k;
-    if (i < count) data[i] += add;
+// ... and every tile adds its offset.
+__device__ __forceinline__ void scan_add(Blk k, uint32_t *data, int64_t count, const uint32_t *bsum) {
+  const int64_t tiles = (count + kScanTile - 1) / kScanTile;
+  for (int64_t t = k.b; t < tiles; t += k.nb) {
+    const uint32_t add = bsum[t];
+    for (int j = threadIdx.x; j < kScanTile; j += kBlock) {
+      const int64_t i = t * kScanTile + j;
+      if (i < count) data[i] += add;
+    }
   }
 }
 
-// ---- grid build ----
-
 // Cell key of every point (row-major over the cell coordinates, last dimension
 // fastest) and its slot in the cell.  Out-of-range coordinates are clamped and flagged.
-__global__ void k_cell_keys(const int32_t *__restrict__ pts, Plan p, uint32_t *__restrict__ cnt,
-                            uint32_t *__restrict__ key, uint32_t *__restrict__ slot,
-                            DevHeader *__restrict__ hdr) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  uint32_t k = 0;
-  bool bad = false;
-  for (int t = 0; t < p.d; ++t) {
-    int32_t x = pts[i * p.d + t];
-    if (x < 0 || x >= DPC_COORD_LIMIT) {
-      bad = true;
-      x = x < 0 ? 0 : DPC_COORD_LIMIT - 1;
+__device__ __forceinline__ void cell_keys(Blk k, const int32_t *__restrict__ pts, const Plan &p,
+                                          uint32_t *__restrict__ cnt, uint32_t *__restrict__ key,
+                                          uint32_t *__restrict__ slot, DevHeader *__restrict__ hdr) {
+  for (int64_t i = thread_index(k); i < p.n; i += grid_threads(k)) {
+    uint32_t kk = 0;
+    bool bad = false;
+    for (int t = 0; t < p.d; ++t) {
+      int32_t x = pts[i * p.d + t];
+      if (x < 0 || x >= DPC_COORD_LIMIT) {
+        bad = true;
+        x = x < 0 ? 0 : DPC_COORD_LIMIT - 1;
+      }
+      kk = kk * uint32_t(p.nc) + uint32_t(x / p.L);
     }
-    k = k * uint32_t(p.nc) + uint32_t(x / p.L);
+    if (bad) atomicOr(&hdr->status, 1u);
+    key[i] = kk;
+    slot[i] = atomicAdd(&cnt[kk], 1u);
   }
-  if (bad) atomicOr(&hdr->status, 1u);
-  key[i] = k;
-  slot[i] = atomicAdd(&cnt[k], 1u);
 }
 
 // Place every point at start[key] + slot: clamped coordinates, their packed low
 // 16 bits, and the id.
-__global__ void k_scatter(const int32_t *__restrict__ pts, Plan p, const uint32_t *__restrict__ start,
-                          const uint32_t *__restrict__ key, const uint32_t *__restrict__ slot,
-                          int32_t *__restrict__ spts, uint32_t *__restrict__ spk, int32_t *__restrict__ sid) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= p.n) return;
-  const int64_t pos = int64_t(start[key[i]]) + slot[i];
-  uint32_t w = 0;
-  for (int t = 0; t < p.d; ++t) {
-    int32_t x = pts[i * p.d + t];
-    x = x < 0 ? 0 : (x >= DPC_COORD_LIMIT ? DPC_COORD_LIMIT - 1 : x);
-    spts[pos * p.d + t] = x;
-    w |= (uint32_t(x) & 0xFFFFu) << (16 * (t & 1));
-    if (t & 1) {
-      spk[pos * p.words + (t >> 1)] = w;
-      w = 0;
+__device__ __forceinline__ void scatter(Blk k, const int32_t *__restrict__ pts, const Plan &p,
+                                        const uint32_t *__restrict__ start, const uint32_t *__restrict__ key,
+                                        const uint32_t *__restrict__ slot, int32_t *__restrict__ spts,
+                                        uint32_t *__restrict__ spk, int32_t *__restrict__ sid) {
+  for (int64_t i = thread_index(k); i < p.n; i += grid_threads(k)) {
+    const int64_t pos = int64_t(start[key[i]]) + slot[i];
+    uint32_t w = 0;
+    for (int t = 0; t < p.d; ++t) {
+      int32_t x = pts[i * p.d + t];
+      x = x < 0 ? 0 : (x >= DPC_COORD_LIMIT ? DPC_COORD_LIMIT - 1 : x);
+      spts[pos * p.d + t] = x;
+      w |= (uint32_t(x) & 0xFFFFu) << (16 * (t & 1));
+      if (t & 1) {
+        spk[pos * p.words + (t >> 1)] = w;
+        w = 0;
+      }
     }
+    if (p.d & 1) spk[pos * p.words + (p.d >> 1)] = w;
+    sid[pos] = int32_t(i);
   }
-  if (p.d & 1) spk[pos * p.words + (p.d >> 1)] = w;
-  sid[pos] = int32_t(i);
 }
 
 // A strip is wc consecutive cells of one row (all coordinates but the last fixed).
@@ -151,106 +160,115 @@ __device__ __forceinline__ void strip_range(const Plan &p, int64_t s, const uint
   *e = start[k1];
 }
 
-__global__ void k_strip_count(Plan p, const uint32_t *__restrict__ start, uint32_t *__restrict__ tcnt) {
-  int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s >= p.nstrips) return;
-  uint32_t b, e;
-  strip_range(p, s, start, &b, &e);
-  tcnt[s] = (e - b + kQueryChunk - 1) / kQueryChunk;
+// Tasks per strip; the entry past the last strip is cleared for the scan.
+__device__ __forceinline__ void strip_count(Blk k, const Plan &p, const uint32_t *__restrict__ start,
+                                            uint32_t *__restrict__ tcnt) {
+  for (int64_t s = thread_index(k); s <= p.nstrips; s += grid_threads(k)) {
+    uint32_t c = 0;
+    if (s < p.nstrips) {
+      uint32_t b, e;
+      strip_range(p, s, start, &b, &e);
+      c = (e - b + kQueryChunk - 1) / kQueryChunk;
+    }
+    tcnt[s] = c;
+  }
 }
 
-__global__ void k_strip_tasks(Plan p, const uint32_t *__restrict__ start, const uint32_t *__restrict__ toff,
-                              uint4 *__restrict__ tasks, DevHeader *__restrict__ hdr) {
-  int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s == 0) hdr->ntasks = toff[p.nstrips];
-  if (s >= p.nstrips) return;
-  uint32_t b, e;
-  strip_range(p, s, start, &b, &e);
-  uint32_t t = toff[s];
-  for (uint32_t q = b; q < e; q += kQueryChunk, ++t)
-    tasks[t] = make_uint4(q, min(q + uint32_t(kQueryChunk), e), uint32_t(s), 0u);
+__device__ __forceinline__ void strip_tasks(Blk k, const Plan &p, const uint32_t *__restrict__ start,
+                                            const uint32_t *__restrict__ toff, uint4 *__restrict__ tasks,
+                                            DevHeader *__restrict__ hdr) {
+  for (int64_t s = thread_index(k); s < p.nstrips; s += grid_threads(k)) {
+    if (s == 0) hdr->ntasks = toff[p.nstrips];
+    uint32_t b, e;
+    strip_range(p, s, start, &b, &e);
+    uint32_t t = toff[s];
+    for (uint32_t q = b; q < e; q += kQueryChunk, ++t)
+      tasks[t] = make_uint4(q, min(q + uint32_t(kQueryChunk), e), uint32_t(s), 0u);
+  }
 }
 
 // (rho << 32) | ~id for every cell-order position, from the caller's rho.  A
 // density outside [1, n] (not produced by dpc_density) is clamped and flagged,
 // so every bucket index stays in range.
-__global__ void k_gather_rank_keys(Plan p, const int32_t *__restrict__ rho, const int32_t *__restrict__ sid,
-                                   uint64_t *__restrict__ sK, DevHeader *__restrict__ hdr) {
-  int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= p.n) return;
-  const int32_t id = sid[q];
-  int64_t r = rho[id];
-  if (r < 1 || r > p.n) {
-    atomicOr(&hdr->status, 2u);
-    r = r < 1 ? 1 : p.n;
+__device__ __forceinline__ void gather_keys(Blk k, const Plan &p, const int32_t *__restrict__ rho,
+                                            const int32_t *__restrict__ sid, uint64_t *__restrict__ sK,
+                                            DevHeader *__restrict__ hdr) {
+  for (int64_t q = thread_index(k); q < p.n; q += grid_threads(k)) {
+    const int32_t id = sid[q];
+    int64_t r = rho[id];
+    if (r < 1 || r > p.n) {
+      atomicOr(&hdr->status, 2u);
+      r = r < 1 ? 1 : p.n;
+    }
+    sK[q] = (uint64_t(r) << 32) | uint32_t(~uint32_t(id));
   }
-  sK[q] = (uint64_t(r) << 32) | uint32_t(~uint32_t(id));
 }
 
 // ---- density-rank sort: order by rho descending; equal rho share a bucket ----
 
 // Bucket slots of the density-rank sort.  Most densities are small and many
-// points share one, so a block first counts its small densities in LDS and then
-// claims each bucket's slots with one global atomic; densities of kRankBins or
-// more take a global atomic each.
+// points share one, so a block first counts a chunk's small densities in LDS and
+// then claims each bucket's slots with one global atomic; densities of kRankBins
+// or more take a global atomic each.
 constexpr int kRankBins = 2048;
-constexpr int kRankItems = 4;  // points per thread
+constexpr int kRankItems = 4;  // points per thread and chunk
+constexpr int64_t kRankChunk = int64_t(kBlock) * kRankItems;
 
-__global__ __launch_bounds__(kBlock) void k_rank_hist(Plan p, const uint64_t *__restrict__ sK,
-                                                      uint32_t *__restrict__ rcnt, uint32_t *__restrict__ slot) {
+__device__ __forceinline__ void rank_hist(Blk k, const Plan &p, const uint64_t *__restrict__ sK,
+                                          uint32_t *__restrict__ rcnt, uint32_t *__restrict__ slot) {
   __shared__ uint32_t bins[kRankBins];
-  for (int b = threadIdx.x; b < kRankBins; b += kBlock) bins[b] = 0;
-  __syncthreads();
-  const int64_t base = int64_t(blockIdx.x) * kBlock * kRankItems;
-  uint32_t local[kRankItems];
-  int64_t rho[kRankItems];
+  const int64_t chunks = (p.n + kRankChunk - 1) / kRankChunk;
+  for (int64_t c = k.b; c < chunks; c += k.nb) {
+    for (int b = threadIdx.x; b < kRankBins; b += kBlock) bins[b] = 0;
+    __syncthreads();
+    const int64_t base = c * kRankChunk;
+    uint32_t local[kRankItems];
+    int64_t rho[kRankItems];
 #pragma unroll
-  for (int k = 0; k < kRankItems; ++k) {
-    const int64_t q = base + int64_t(k) * kBlock + threadIdx.x;
-    rho[k] = 0;
-    local[k] = 0;
-    if (q < p.n) {
-      int64_t r = int64_t(sK[q] >> 32);
-      r = r < 1 ? 1 : (r > p.n ? p.n : r);
-      rho[k] = r;
-      if (r <= kRankBins)
-        local[k] = atomicAdd(&bins[r - 1], 1u);
-      else
-        slot[q] = atomicAdd(&rcnt[p.n - r], 1u);
+    for (int j = 0; j < kRankItems; ++j) {
+      const int64_t q = base + int64_t(j) * kBlock + threadIdx.x;
+      rho[j] = 0;
+      local[j] = 0;
+      if (q < p.n) {
+        int64_t r = int64_t(sK[q] >> 32);
+        r = r < 1 ? 1 : (r > p.n ? p.n : r);
+        rho[j] = r;
+        if (r <= kRankBins)
+          local[j] = atomicAdd(&bins[r - 1], 1u);
+        else
+          slot[q] = atomicAdd(&rcnt[p.n - r], 1u);
+      }
     }
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < kRankBins; b += kBlock) {
-    const uint32_t c = bins[b];
-    if (c && b + 1 <= p.n) bins[b] = atomicAdd(&rcnt[p.n - (b + 1)], c);
-  }
-  __syncthreads();
+    __syncthreads();
+    for (int b = threadIdx.x; b < kRankBins; b += kBlock) {
+      const uint32_t cnt = bins[b];
+      if (cnt && b + 1 <= p.n) bins[b] = atomicAdd(&rcnt[p.n - (b + 1)], cnt);
+    }
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kRankItems; ++k) {
-    const int64_t q = base + int64_t(k) * kBlock + threadIdx.x;
-    if (q < p.n && rho[k] <= kRankBins) slot[q] = bins[rho[k] - 1] + local[k];
+    for (int j = 0; j < kRankItems; ++j) {
+      const int64_t q = base + int64_t(j) * kBlock + threadIdx.x;
+      if (q < p.n && rho[j] <= kRankBins) slot[q] = bins[rho[j] - 1] + local[j];
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_rank_scatter(Plan p, const uint64_t *__restrict__ sK, const uint32_t *__restrict__ rstart,
-                               const uint32_t *__restrict__ slot, const int32_t *__restrict__ spts,
-                               const int32_t *__restrict__ sid, int32_t *__restrict__ rpts,
-                               int32_t *__restrict__ rid) {
-  int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= p.n) return;
-  int64_t rho = int64_t(sK[q] >> 32);
-  rho = rho < 1 ? 1 : (rho > p.n ? p.n : rho);
-  const int64_t r = int64_t(rstart[p.n - rho]) + slot[q];
-  for (int t = 0; t < p.d; ++t) rpts[r * p.d + t] = spts[q * p.d + t];
-  rid[r] = sid[q];
-}
-
-__global__ void k_clear_status(DevHeader *hdr) {
-  if (threadIdx.x == 0) hdr->status = 0;
+__device__ __forceinline__ void rank_scatter(Blk k, const Plan &p, const uint64_t *__restrict__ sK,
+                                             const uint32_t *__restrict__ rstart, const uint32_t *__restrict__ slot,
+                                             const int32_t *__restrict__ spts, const int32_t *__restrict__ sid,
+                                             int32_t *__restrict__ rpts, int32_t *__restrict__ rid) {
+  for (int64_t q = thread_index(k); q < p.n; q += grid_threads(k)) {
+    int64_t rho = int64_t(sK[q] >> 32);
+    rho = rho < 1 ? 1 : (rho > p.n ? p.n : rho);
+    const int64_t r = int64_t(rstart[p.n - rho]) + slot[q];
+    for (int t = 0; t < p.d; ++t) rpts[r * p.d + t] = spts[q * p.d + t];
+    rid[r] = sid[q];
+  }
 }
 
 // Work counters of one call; `grid` also clears the task count of the grid build.
-__global__ void k_reset_counters(DevHeader *hdr, int grid) {
+__device__ __forceinline__ void reset_hdr(DevHeader *hdr, int grid) {
   if (threadIdx.x == 0) {
     if (grid) hdr->ntasks = 0;
     hdr->n_unres = 0;
@@ -258,7 +276,170 @@ __global__ void k_reset_counters(DevHeader *hdr, int grid) {
   }
 }
 
+// ---- single-job kernels ----
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, int64_t count) {
+  fill_u32(grid_blk(), p, v, count);
+}
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *data, int64_t count, uint32_t *bsum) {
+  scan_tiles(grid_blk(), data, count, bsum);
+}
+__global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t *bsum, int64_t count) { scan_sums(bsum, count); }
+__global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *data, int64_t count, const uint32_t *bsum) {
+  scan_add(grid_blk(), data, count, bsum);
+}
+__global__ __launch_bounds__(kBlock) void k_cell_keys(const int32_t *pts, Plan p, Ws w) {
+  cell_keys(grid_blk(), pts, p, w.cnt, w.key, w.slot, w.hdr);
+}
+__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t *pts, Plan p, Ws w) {
+  scatter(grid_blk(), pts, p, w.cnt, w.key, w.slot, w.spts, w.spk, w.sid);
+}
+__global__ __launch_bounds__(kBlock) void k_strip_count(Plan p, Ws w) { strip_count(grid_blk(), p, w.cnt, w.tcnt); }
+__global__ __launch_bounds__(kBlock) void k_strip_tasks(Plan p, Ws w) {
+  strip_tasks(grid_blk(), p, w.cnt, w.tcnt, w.tasks, w.hdr);
+}
+__global__ __launch_bounds__(kBlock) void k_gather_rank_keys(Plan p, const int32_t *rho, Ws w) {
+  gather_keys(grid_blk(), p, rho, w.sid, w.sK, w.hdr);
+}
+__global__ __launch_bounds__(kBlock) void k_rank_hist(Plan p, Ws w) { rank_hist(grid_blk(), p, w.sK, w.rcnt, w.slot); }
+__global__ __launch_bounds__(kBlock) void k_rank_scatter(Plan p, Ws w) {
+  rank_scatter(grid_blk(), p, w.sK, w.rcnt, w.slot, w.spts, w.sid, w.rpts, w.rid);
+}
+__global__ void k_clear_status(DevHeader *hdr) {
+  if (threadIdx.x == 0) hdr->status = 0;
+}
+__global__ void k_reset_counters(DevHeader *hdr, int grid) { reset_hdr(hdr, grid); }
+
+// ---- many-job kernels: virtual block v of map m runs the body for its job ----
+
+#define DPC_FOR_VBLOCKS(m)                                             \
+  for (uint32_t v = (m).v0 + blockIdx.x; v < (m).v1; v += gridDim.x) { \
+    const uint32_t j = vjob_of((m), v);                                \
+    const Blk k = vblk_of((m), v, j);                                  \
+    const Plan p = load_uniform(&jobs[j].p);                                \
+    const Ws w = load_uniform(&jobs[j].w);
+
+// The arrays the batched scans and fills work on.
+enum ScanArr { kArrCells = 0, kArrStrips = 1, kArrRank = 2 };
+
+template <int A>
+__device__ __forceinline__ void scan_target(const Plan &p, const Ws &w, uint32_t **data, int64_t *count) {
+  if (A == kArrCells) {
+    *data = w.cnt;
+    *count = p.ncells + 1;
+  } else if (A == kArrStrips) {
+    *data = w.tcnt;
+    *count = p.nstrips + 1;
+  } else {
+    *data = w.rcnt;
+    *count = p.n + 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_start(const JobDev *jobs, VMap m, int grid) {
+  DPC_FOR_VBLOCKS(m)
+  (void)k;
+  (void)p;
+  if (threadIdx.x == 0) w.hdr->status = 0;
+  reset_hdr(w.hdr, grid);
+}
+}
+
+template <int A>
+__global__ __launch_bounds__(kBlock) void kb_fill(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  uint32_t *data;
+  int64_t count;
+  scan_target<A>(p, w, &data, &count);
+  fill_u32(k, data, 0u, count);
+}
+}
+
+template <int A>
+__global__ __launch_bounds__(kBlock) void kb_scan_tiles(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  uint32_t *data;
+  int64_t count;
+  scan_target<A>(p, w, &data, &count);
+  scan_tiles(k, data, count, w.bsum);
+}
+}
+
+template <int A>
+__global__ __launch_bounds__(kBlock) void kb_scan_sums(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  (void)k;
+  uint32_t *data;
+  int64_t count;
+  scan_target<A>(p, w, &data, &count);
+  scan_sums(w.bsum, count);
+}
+}
+
+template <int A>
+__global__ __launch_bounds__(kBlock) void kb_scan_add(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  uint32_t *data;
+  int64_t count;
+  scan_target<A>(p, w, &data, &count);
+  scan_add(k, data, count, w.bsum);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_cell_keys(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  cell_keys(k, as_const(jobs)[j].pts, p, w.cnt, w.key, w.slot, w.hdr);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_scatter(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  scatter(k, as_const(jobs)[j].pts, p, w.cnt, w.key, w.slot, w.spts, w.spk, w.sid);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_strip_count(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  strip_count(k, p, w.cnt, w.tcnt);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_strip_tasks(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  strip_tasks(k, p, w.cnt, w.tcnt, w.tasks, w.hdr);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_gather_rank_keys(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  gather_keys(k, p, as_const(jobs)[j].rho, w.sid, w.sK, w.hdr);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_rank_hist(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  rank_hist(k, p, w.sK, w.rcnt, w.slot);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_rank_scatter(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  rank_scatter(k, p, w.sK, w.rcnt, w.slot, w.spts, w.sid, w.rpts, w.rid);
+}
+}
+
+#undef DPC_FOR_VBLOCKS
+
+template <int A>
+void batch_scan(const BatchMaps &B, const VMap &tiles, hipStream_t s) {
+  if (vgrid(tiles)) DPC_LAUNCH((kb_scan_tiles<A>), vgrid(tiles), kBlock, s, B.jobs, tiles);
+  if (vgrid(B.one)) DPC_LAUNCH((kb_scan_sums<A>), vgrid(B.one), kBlock, s, B.jobs, B.one);
+  if (vgrid(tiles)) DPC_LAUNCH((kb_scan_add<A>), vgrid(tiles), kBlock, s, B.jobs, tiles);
+}
+
 }  // namespace
+
+// ---- single-job host side ----
 
 hipError_t launch_fill_u32(uint32_t *ptr, uint32_t value, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
@@ -272,7 +453,7 @@ hipError_t launch_scan(uint32_t *data, int64_t count, uint32_t *bsum, hipStream_
   if (count <= 0) return hipSuccess;
   const unsigned tiles = blocks_for(count, kScanTile);
   DPC_LAUNCH((k_scan_tiles), tiles, kBlock, s, data, count, bsum);
-  DPC_LAUNCH((k_scan_sums), 1, kBlock, s, bsum, tiles);
+  DPC_LAUNCH((k_scan_sums), 1, kBlock, s, bsum, count);
   DPC_LAUNCH((k_scan_add), tiles, kBlock, s, data, count, bsum);
   return hipGetLastError();
 }
@@ -291,28 +472,55 @@ hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, hipStream_
   hipError_t e;
   if ((e = reset_counters(w.hdr, true, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(w.cnt, 0u, p.ncells + 1, s)) != hipSuccess) return e;
-  DPC_LAUNCH((k_cell_keys), blocks_for(p.n, kBlock), kBlock, s, pts, p, w.cnt, w.key, w.slot, w.hdr);
+  DPC_LAUNCH((k_cell_keys), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
   if ((e = launch_scan(w.cnt, p.ncells + 1, w.bsum, s)) != hipSuccess) return e;
-  DPC_LAUNCH((k_scatter), blocks_for(p.n, kBlock), kBlock, s, pts, p, w.cnt, w.key, w.slot, w.spts, w.spk, w.sid);
-  DPC_LAUNCH((k_strip_count), blocks_for(p.nstrips, kBlock), kBlock, s, p, w.cnt, w.tcnt);
-  if ((e = launch_fill_u32(w.tcnt + p.nstrips, 0u, 1, s)) != hipSuccess) return e;
+  DPC_LAUNCH((k_scatter), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
+  DPC_LAUNCH((k_strip_count), blocks_for(p.nstrips + 1, kBlock), kBlock, s, p, w);
   if ((e = launch_scan(w.tcnt, p.nstrips + 1, w.bsum, s)) != hipSuccess) return e;
-  DPC_LAUNCH((k_strip_tasks), blocks_for(p.nstrips, kBlock), kBlock, s, p, w.cnt, w.tcnt, w.tasks, w.hdr);
+  DPC_LAUNCH((k_strip_tasks), blocks_for(p.nstrips, kBlock), kBlock, s, p, w);
   return hipGetLastError();
 }
 
 hipError_t gather_rank_keys(const Plan &p, const Ws &w, const int32_t *rho, hipStream_t s) {
-  DPC_LAUNCH((k_gather_rank_keys), blocks_for(p.n, kBlock), kBlock, s, p, rho, w.sid, w.sK, w.hdr);
+  DPC_LAUNCH((k_gather_rank_keys), blocks_for(p.n, kBlock), kBlock, s, p, rho, w);
   return hipGetLastError();
 }
 
 hipError_t rank_sort(const Plan &p, const Ws &w, hipStream_t s) {
   hipError_t e;
   if ((e = launch_fill_u32(w.rcnt, 0u, p.n + 1, s)) != hipSuccess) return e;
-  DPC_LAUNCH((k_rank_hist), blocks_for(p.n, kBlock * kRankItems), kBlock, s, p, w.sK, w.rcnt, w.slot);
+  DPC_LAUNCH((k_rank_hist), blocks_for(p.n, int(kRankChunk)), kBlock, s, p, w);
   if ((e = launch_scan(w.rcnt, p.n + 1, w.bsum, s)) != hipSuccess) return e;
-  DPC_LAUNCH((k_rank_scatter), blocks_for(p.n, kBlock), kBlock, s, p, w.sK, w.rcnt, w.slot, w.spts, w.sid, w.rpts,
-                                                           w.rid);
+  DPC_LAUNCH((k_rank_scatter), blocks_for(p.n, kBlock), kBlock, s, p, w);
+  return hipGetLastError();
+}
+
+// ---- many-job host side ----
+
+hipError_t batch_start(const BatchMaps &B, hipStream_t s) {
+  if (vgrid(B.one)) DPC_LAUNCH((kb_start), vgrid(B.one), kBlock, s, B.jobs, B.one, 1);
+  return hipGetLastError();
+}
+
+hipError_t batch_build_grid(const BatchMaps &B, hipStream_t s) {
+  if (vgrid(B.cells)) DPC_LAUNCH((kb_fill<kArrCells>), vgrid(B.cells), kBlock, s, B.jobs, B.cells);
+  if (vgrid(B.pts)) DPC_LAUNCH((kb_cell_keys), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  batch_scan<kArrCells>(B, B.cells, s);
+  if (vgrid(B.pts)) DPC_LAUNCH((kb_scatter), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  if (vgrid(B.strips)) DPC_LAUNCH((kb_strip_count), vgrid(B.strips), kBlock, s, B.jobs, B.strips);
+  batch_scan<kArrStrips>(B, B.strips, s);
+  if (vgrid(B.strips)) DPC_LAUNCH((kb_strip_tasks), vgrid(B.strips), kBlock, s, B.jobs, B.strips);
+  return hipGetLastError();
+}
+
+hipError_t batch_rank(const BatchMaps &B, hipStream_t s) {
+  if (vgrid(B.pts)) {
+    DPC_LAUNCH((kb_gather_rank_keys), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+    DPC_LAUNCH((kb_fill<kArrRank>), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+    DPC_LAUNCH((kb_rank_hist), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  }
+  batch_scan<kArrRank>(B, B.pts, s);
+  if (vgrid(B.pts)) DPC_LAUNCH((kb_rank_scatter), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   return hipGetLastError();
 }
 

@@ -39,6 +39,34 @@ class PlanInfo(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    """dpc_tuning: plan options of one problem (0 = default)."""
+    _fields_ = [("subdiv", ctypes.c_int32), ("strip_cells", ctypes.c_int32), ("nstages", ctypes.c_int32),
+                ("stage_radius", ctypes.c_int32 * 4), ("stage_group", ctypes.c_int32 * 4),
+                ("ring_cap", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, subdiv=0, strip_cells=0, stages=(), ring_cap=0) -> "Tuning":
+        t = cls()
+        t.subdiv, t.strip_cells, t.ring_cap = int(subdiv), int(strip_cells), int(ring_cap)
+        t.nstages = len(stages)
+        for k, (radius, group) in enumerate(stages):
+            t.stage_radius[k], t.stage_group[k] = int(radius), int(group)
+        return t
+
+    def as_dict(self) -> dict:
+        return {"subdiv": self.subdiv, "strip_cells": self.strip_cells, "ring_cap": self.ring_cap,
+                "stages": [(self.stage_radius[k], self.stage_group[k]) for k in range(self.nstages)]}
+
+
+class Job(ctypes.Structure):
+    """dpc_job: one problem of a batch (device pointers)."""
+    _fields_ = [("pts", ctypes.c_void_p), ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("d_cut", ctypes.c_double),
+                ("rho_min", ctypes.c_int32), ("delta_min", ctypes.c_double), ("rho", ctypes.c_void_p),
+                ("dep", ctypes.c_void_p), ("delta", ctypes.c_void_p), ("label", ctypes.c_void_p),
+                ("ncenters", ctypes.c_void_p)]
+
+
 def lib() -> ctypes.CDLL:
     """Load libdpc.so (raises if it has not been built)."""
     global _lib
@@ -59,6 +87,14 @@ def lib() -> ctypes.CDLL:
             "dpc_version": (I32, []),
             "dpc_cutoff_square": (I64, [D]),
             "dpc_plan": (I32, [I64, I32, D, ctypes.POINTER(PlanInfo)]),
+            "dpc_plan_tuned": (I32, [I64, I32, D, ctypes.POINTER(Tuning), ctypes.POINTER(PlanInfo)]),
+            "dpc_batch_plan": (I32, [ctypes.POINTER(Job), I32, ctypes.POINTER(Tuning), ctypes.POINTER(P),
+                                     ctypes.POINTER(SZ)]),
+            "dpc_batch_bind": (I32, [P, P, SZ]),
+            "dpc_batch_run": (I32, [P, P, P]),
+            "dpc_batch_sync_status": (I32, [P, P, P, ctypes.POINTER(I32)]),
+            "dpc_batch_job_plan": (I32, [P, I32, ctypes.POINTER(PlanInfo)]),
+            "dpc_batch_free": (None, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -99,6 +135,13 @@ def dpc_cutoff_square(d_cut: float) -> int:
 def dpc_plan(n: int, d: int, d_cut: float) -> dict:
     info = PlanInfo()
     _check(lib().dpc_plan(int(n), int(d), float(d_cut), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def dpc_plan_tuned(n: int, d: int, d_cut: float, tuning: Tuning | None = None) -> dict:
+    info = PlanInfo()
+    _check(lib().dpc_plan_tuned(int(n), int(d), float(d_cut), ctypes.byref(tuning) if tuning else None,
+                                ctypes.byref(info)))
     return info.as_dict()
 
 
@@ -183,3 +226,90 @@ def dpc_run(pts: torch.Tensor, d_cut: float, rho_min: int, delta_min: float, ws:
 def dpc_sync_status(ws: torch.Tensor, stream=None) -> None:
     """Synchronise and raise DpcError if the device flagged an error on this workspace."""
     _check(lib().dpc_sync_status(_ptr(ws), _stream(stream)))
+
+
+# ---------------------------------------------------------------- batches
+
+def dpc_batch_plan(jobs, tunings=None) -> tuple[ctypes.c_void_p, int]:
+    """Plan a batch of Job structs; returns (handle, workspace bytes)."""
+    arr = (Job * len(jobs))(*jobs)
+    tarr = None if tunings is None else (Tuning * len(jobs))(*tunings)
+    handle, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
+    _check(lib().dpc_batch_plan(arr, len(jobs), tarr, ctypes.byref(handle), ctypes.byref(nbytes)))
+    return handle, int(nbytes.value)
+
+
+def dpc_batch_bind(handle, ws: torch.Tensor) -> None:
+    _check(lib().dpc_batch_bind(handle, _ptr(ws), ws.numel()))
+
+
+def dpc_batch_run(handle, ws: torch.Tensor, stream=None) -> None:
+    _check(lib().dpc_batch_run(handle, _ptr(ws), _stream(stream)))
+
+
+def dpc_batch_sync_status(handle, ws: torch.Tensor, stream=None) -> int:
+    """Synchronise; raise DpcError (naming the first bad job) if any job flagged an error."""
+    bad = ctypes.c_int32(-1)
+    st = lib().dpc_batch_sync_status(handle, _ptr(ws), _stream(stream), ctypes.byref(bad))
+    if st != DPC_OK:
+        raise DpcError(st, f"job {bad.value}: " + lib().dpc_last_error().decode())
+    return bad.value
+
+
+def dpc_batch_job_plan(handle, i: int) -> dict:
+    info = PlanInfo()
+    _check(lib().dpc_batch_job_plan(handle, int(i), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def dpc_batch_free(handle) -> None:
+    if handle:
+        lib().dpc_batch_free(handle)
+
+
+class Batch:
+    """Many problems run with one launch per phase (dpc_batch_*).
+
+    ``problems`` is a list of (pts, d_cut, rho_min, delta_min) with pts an int32
+    [n, d] device tensor.  Outputs are allocated here, one dict per problem with
+    rho, dep, delta, label and ncenters; ``run()`` refills them.
+    """
+
+    def __init__(self, problems, tunings=None, device="cuda"):
+        self.out, jobs = [], []
+        for pts, d_cut, rho_min, delta_min in problems:
+            n, d = _pts(pts)
+            o = {"rho": torch.empty(n, dtype=torch.int32, device=pts.device),
+                 "dep": torch.empty(n, dtype=torch.int32, device=pts.device),
+                 "delta": torch.empty(n, dtype=torch.float64, device=pts.device),
+                 "label": torch.empty(n, dtype=torch.int32, device=pts.device),
+                 "ncenters": torch.empty(1, dtype=torch.int64, device=pts.device)}
+            self.out.append(o)
+            jobs.append(Job(pts.data_ptr(), n, d, float(d_cut), int(rho_min), float(delta_min), o["rho"].data_ptr(),
+                            o["dep"].data_ptr(), o["delta"].data_ptr(), o["label"].data_ptr(),
+                            o["ncenters"].data_ptr()))
+        self._inputs = [p[0] for p in problems]  # keep the points alive
+        self.handle, nbytes = dpc_batch_plan(jobs, tunings)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        dpc_batch_bind(self.handle, self.ws)
+
+    def run(self, stream=None) -> list[dict]:
+        dpc_batch_run(self.handle, self.ws, stream)
+        return self.out
+
+    def sync_status(self, stream=None) -> int:
+        return dpc_batch_sync_status(self.handle, self.ws, stream)
+
+    def job_plan(self, i: int) -> dict:
+        return dpc_batch_job_plan(self.handle, i)
+
+    def close(self) -> None:
+        dpc_batch_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                self.close()
+        except Exception:
+            pass

@@ -3,15 +3,87 @@
 // rho_min, double delta_min, int32 points[n*d].  Output file: int32 status of
 // dpc_run, int32 status of dpc_sync_status, int64 ncenters, then rho, dep,
 // delta and label arrays.
+//
+// With --batch the input holds int32 njobs and then njobs such records; all
+// jobs run through dpc_batch_run and the output holds one record per job
+// (the status fields are those of the batch calls).
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "dpc.h"
 
+struct Rec {
+  int64_t n;
+  int32_t d, rho_min;
+  double d_cut, delta_min;
+  std::vector<int32_t> pts, rho, dep, label;
+  std::vector<double> delta;
+  int64_t ncenters = -1;
+};
+
+bool read_rec(FILE *in, Rec &r) {
+  if (std::fread(&r.n, 8, 1, in) != 1 || std::fread(&r.d, 4, 1, in) != 1 || std::fread(&r.d_cut, 8, 1, in) != 1 ||
+      std::fread(&r.rho_min, 4, 1, in) != 1 || std::fread(&r.delta_min, 8, 1, in) != 1)
+    return false;
+  r.pts.resize(size_t(r.n) * r.d);
+  if (std::fread(r.pts.data(), 4, r.pts.size(), in) != r.pts.size()) return false;
+  r.rho.resize(r.n);
+  r.dep.resize(r.n);
+  r.label.resize(r.n);
+  r.delta.resize(r.n);
+  return true;
+}
+
+void write_rec(FILE *out, int32_t st, int32_t st2, const Rec &r) {
+  std::fwrite(&st, 4, 1, out);
+  std::fwrite(&st2, 4, 1, out);
+  std::fwrite(&r.ncenters, 8, 1, out);
+  std::fwrite(r.rho.data(), 4, r.n, out);
+  std::fwrite(r.dep.data(), 4, r.n, out);
+  std::fwrite(r.delta.data(), 8, r.n, out);
+  std::fwrite(r.label.data(), 4, r.n, out);
+}
+
+int run_batch(const char *inp, const char *outp) {
+  FILE *in = std::fopen(inp, "rb");
+  if (!in) return 2;
+  int32_t njobs = 0;
+  if (std::fread(&njobs, 4, 1, in) != 1 || njobs < 1) return 2;
+  std::vector<Rec> recs(njobs);
+  for (auto &r : recs)
+    if (!read_rec(in, r)) return 2;
+  std::fclose(in);
+  std::vector<dpc_job> jobs(njobs);
+  for (int32_t i = 0; i < njobs; ++i) {
+    Rec &r = recs[i];
+    jobs[i] = dpc_job{r.pts.data(), r.n, r.d, r.d_cut, r.rho_min, r.delta_min, r.rho.data(), r.dep.data(),
+                      r.delta.data(), r.label.data(), &r.ncenters};
+  }
+  dpc_batch *b = nullptr;
+  size_t wsb = 0;
+  int32_t st = dpc_batch_plan(jobs.data(), njobs, nullptr, &b, &wsb);
+  int32_t st2 = st;
+  if (st == DPC_OK) {
+    void *ws = std::aligned_alloc(256, (wsb + 255) / 256 * 256);
+    st = dpc_batch_bind(b, ws, wsb);
+    if (st == DPC_OK) st = dpc_batch_run(b, ws, nullptr);
+    int32_t bad = -1;
+    st2 = dpc_batch_sync_status(b, ws, nullptr, &bad);
+    std::free(ws);
+    dpc_batch_free(b);
+  }
+  FILE *out = std::fopen(outp, "wb");
+  for (auto &r : recs) write_rec(out, st, st2, r);
+  std::fclose(out);
+  return 0;
+}
+
 int main(int argc, char **argv) {
+  if (argc == 4 && std::string(argv[1]) == "--batch") return run_batch(argv[2], argv[3]);
   if (argc != 3) {
-    std::fprintf(stderr, "usage: %s input output\n", argv[0]);
+    std::fprintf(stderr, "usage: %s [--batch] input output\n", argv[0]);
     return 2;
   }
   FILE *in = std::fopen(argv[1], "rb");

@@ -58,7 +58,7 @@ def test_plan_invariants(n, d, d_cut):
     L, K0 = p["cell_side"], p["window_radius"]
     assert K0 * L >= min(max(1, math.isqrt(R - 1)), dpc.COORD_LIMIT), "(2 K0 + 1)^d cells must hold the d_cut-ball"
     assert p["cells_per_dim"] * L >= dpc.COORD_LIMIT
-    assert p["cells"] == p["cells_per_dim"] ** d <= 1 << 26
+    assert p["cells"] == p["cells_per_dim"] ** d <= min(1 << 26, max(4096, 8 * n))
     if p["mode"] == 0:  # packed 16-bit path: window extent keeps |dx| < 2^15 and D2 < 2^31
         E = (p["strip_cells"] + 2 * K0) * L
         assert E - 1 <= 32767 and d * (E - 1) ** 2 <= 2 ** 31 - 1
@@ -87,3 +87,55 @@ def test_argument_validation_enqueues_nothing():
     # Def. 5 requires delta_min > d_cut.
     assert L.dpc_run(fake, 10, 2, 3.0, 1, 3.0, fake, fake, fake, fake, fake, fake, need, P(0)) == dpc.DPC_EINVAL
     assert L.dpc_workspace_bytes(0, 2, 1.0) == 0
+
+
+def _fake_job(n, d, d_cut, rho_min=1, delta_factor=2.0):
+    f = 4096
+    return dpc.Job(f, n, d, d_cut, rho_min, d_cut * delta_factor, f, f, f, f, f)
+
+
+def test_batch_plan_matches_single_plans_and_sizes():
+    rng = np.random.default_rng(3)
+    specs = [(int(rng.integers(1, 60000)), int(rng.integers(1, 9)), float(rng.uniform(1, 5000))) for _ in range(50)]
+    specs += [(1, 1, 0.5), (1_000_000, 2, 200.0)]
+    handle, nbytes = dpc.dpc_batch_plan([_fake_job(*s) for s in specs])
+    try:
+        total = 0
+        for i, (n, d, dc) in enumerate(specs):
+            want = dpc.dpc_plan(n, d, dc)
+            assert dpc.dpc_batch_job_plan(handle, i) == want, i
+            total += want["workspace_bytes"]
+        assert nbytes >= total
+    finally:
+        dpc.dpc_batch_free(handle)
+
+
+def test_batch_plan_validates_every_job():
+    good = [_fake_job(100, 2, 10.0)] * 3
+    for bad, what in [(_fake_job(100, 9, 10.0), "d"), (_fake_job(0, 2, 10.0), "n"),
+                      (_fake_job(100, 2, float("nan")), "d_cut"), (_fake_job(100, 2, 10.0, rho_min=-1), "rho_min"),
+                      (_fake_job(100, 2, 10.0, delta_factor=1.0), "delta_min")]:
+        with pytest.raises(dpc.DpcError) as e:
+            dpc.dpc_batch_plan(good[:2] + [bad] + good[2:])
+        assert e.value.status == dpc.DPC_EINVAL and "job 2" in str(e.value), what
+    nul = _fake_job(100, 2, 10.0)
+    nul.label = None
+    with pytest.raises(dpc.DpcError):
+        dpc.dpc_batch_plan([nul])
+    L = dpc.lib()
+    h, _ = dpc.dpc_batch_plan(good)
+    try:  # running on a workspace that was never bound is refused before anything is enqueued
+        assert L.dpc_batch_run(h, ctypes.c_void_p(4096), None) == dpc.DPC_EINVAL
+        assert L.dpc_batch_bind(h, ctypes.c_void_p(4096), 16) == dpc.DPC_EWORKSPACE
+    finally:
+        dpc.dpc_batch_free(h)
+
+
+def test_plan_options_are_checked_and_applied():
+    t = dpc.Tuning.make(subdiv=2, strip_cells=5, stages=[(1, 1), (2, 2), (5, 8)], ring_cap=99)
+    p = dpc.dpc_plan_tuned(1_000_000, 2, 200.0, t)
+    assert p["cell_side"] == 100 and p["strip_cells"] == 5 and p["stages"] == 3
+    with pytest.raises(dpc.DpcError):
+        dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(0, 1)]))
+    with pytest.raises(dpc.DpcError):
+        dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(1, 99)]))

@@ -24,25 +24,47 @@ def emu_exe():
     return build_emu.build(os.path.join(ROOT, "_build", "emu"), asan=True)
 
 
-def run_emu(exe, pts, d_cut, rho_min, delta_min):
+def _record(pts, d_cut, rho_min, delta_min):
     pts = np.ascontiguousarray(pts, np.int32)
     n, d = pts.shape
-    with tempfile.TemporaryDirectory() as tmp:
-        fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
-        with open(fin, "wb") as f:
-            f.write(struct.pack("<qidid", n, d, float(d_cut), int(rho_min), float(delta_min)))
-            f.write(pts.tobytes())
-        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:detect_stack_use_after_return=0")
-        r = subprocess.run([exe, fin, fout], capture_output=True, text=True, timeout=600, env=env)
-        assert r.returncode == 0, r.stderr[-3000:]
-        b = open(fout, "rb").read()
-    st, st2, nc = struct.unpack("<iiq", b[:16])
-    o = 16
+    return struct.pack("<qidid", n, d, float(d_cut), int(rho_min), float(delta_min)) + pts.tobytes()
+
+
+def _parse(b, o, n):
+    st, st2, nc = struct.unpack("<iiq", b[o:o + 16])
+    o += 16
     out = {"status": st, "sync": st2, "ncenters": nc}
     for k, dt, sz in (("rho", np.int32, 4), ("dep", np.int32, 4), ("delta", np.float64, 8), ("label", np.int32, 4)):
         out[k] = np.frombuffer(b, dt, n, o).copy()
         o += sz * n
-    return out
+    return out, o
+
+
+def _run(exe, args, payload):
+    with tempfile.TemporaryDirectory() as tmp:
+        fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
+        with open(fin, "wb") as f:
+            f.write(payload)
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:detect_stack_use_after_return=0")
+        r = subprocess.run([exe, *args, fin, fout], capture_output=True, text=True, timeout=600, env=env)
+        assert r.returncode == 0, r.stderr[-3000:]
+        return open(fout, "rb").read()
+
+
+def run_emu(exe, pts, d_cut, rho_min, delta_min):
+    b = _run(exe, [], _record(pts, d_cut, rho_min, delta_min))
+    return _parse(b, 0, int(np.asarray(pts).shape[0]))[0]
+
+
+def run_emu_batch(exe, jobs):
+    """jobs: list of (pts, d_cut, rho_min, delta_min), run through the batch entry points."""
+    payload = struct.pack("<i", len(jobs)) + b"".join(_record(*j) for j in jobs)
+    b = _run(exe, ["--batch"], payload)
+    outs, o = [], 0
+    for j in jobs:
+        out, o = _parse(b, o, int(np.asarray(j[0]).shape[0]))
+        outs.append(out)
+    return outs
 
 
 # The dense cell table spans the whole coordinate domain, so the cut-offs here keep
@@ -80,3 +102,19 @@ def test_emulated_out_of_range_is_flagged_and_bounded(emu_exe):
     assert got["status"] == 0 and got["sync"] == -2
     pins.assert_same(got, pins.run(scan, np.clip(pts, 0, 131071), 2500.0, 1, 4000.0),
                      keys=("rho", "dep", "delta", "label"), ctx="clamped")
+
+
+def test_emulated_batch_matches_oracle(emu_exe):
+    """Jobs of several dimensions and sizes (one of a single point) in one batch."""
+    jobs = []
+    for k, (n, d, dc) in enumerate([(200, 2, 3000.0), (1, 3, 100.0), (333, 1, 40.0), (150, 4, 9000.0),
+                                    (90, 2, 300.0), (40, 6, 20000.0), (12, 8, 30000.0), (257, 3, 5000.0)]):
+        pts = inputs.uniform_points(n, d, 131071, 900 + k)
+        if k % 2:  # duplicates and equal densities
+            pts[n // 2:] = pts[: n - n // 2]
+        jobs.append((pts, dc, 2, dc * 1.7))
+    jobs.append((inputs.blob_job(777, 600, 2, 4, 500.0, 2000.0, 0.05).pts, 900.0, 5, 5000.0))
+    outs = run_emu_batch(emu_exe, jobs)
+    for k, (job, got) in enumerate(zip(jobs, outs)):
+        assert got["status"] == 0 and got["sync"] == 0, k
+        pins.assert_same(got, pins.run(scan, *job), keys=("rho", "dep", "delta", "label", "ncenters"), ctx=f"job {k}")
