@@ -98,6 +98,121 @@ def cpu_baseline(job, budget_s: float) -> dict:
                       f"{job.n} points ({elapsed:.2f} s); points/s scaled by m/n since its cost is O(n^2)"}
 
 
+def _make_job(spec):
+    return spec.make()
+
+
+def make_batch_jobs(count: int):
+    """The batch workload's jobs, drawn in a process pool (before any GPU use)."""
+    import concurrent.futures as cf
+
+    from paper_2207_04649_amd import inputs
+
+    specs = inputs.batch_specs(count)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(workers) as ex:
+        return list(ex.map(_make_job, specs, chunksize=16))
+
+
+def bench_batch(args, jobs) -> int:
+    """Many-job batch: all jobs through dpc_batch_run (one launch per phase and
+    dimension), against the same jobs launched one dpc_run at a time."""
+    import torch
+
+    from paper_2207_04649_amd import autotune, dpc
+
+    dev = torch.device("cuda:0")
+    problems = [(torch.from_numpy(j.pts).to(dev), j.d_cut, j.rho_min, j.delta_min) for j in jobs]
+    total = sum(j.n for j in jobs)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    table = {} if args.no_autotune else autotune.tune(problems, log=log)
+    tun = autotune.tunings_for(problems, table) if table else None
+    b = dpc.Batch(problems, tun)
+    for _ in range(max(1, args.warmup)):
+        b.run()
+    b.sync_status()
+
+    L = dpc.lib()
+    L.dpc_profile_enable.argtypes = [ctypes.c_int32]
+    L.dpc_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    buf = ctypes.create_string_buffer(8192)
+    L.dpc_profile_report(buf, 8192)
+    L.dpc_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.dpc_profile_enable(0)
+    L.dpc_profile_report(buf, 8192)
+    prof = json.loads(buf.value.decode())
+    b.sync_status()
+    batched_s = (t1 - t0) / args.steps
+
+    # The same batch replayed from a captured HIP graph.
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            dpc.dpc_batch_run(b.handle, b.ws, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / args.steps
+    b.sync_status()
+
+    # One dpc_run launch sequence per job, workspaces allocated beforehand.
+    wss = [dpc.workspace(j.n, j.d, j.d_cut, dev) for j in jobs]
+    outs = [{} for _ in jobs]
+    for (pt, dc, rm, dm), ws, o in zip(problems, wss, outs):
+        dpc.dpc_run(pt, dc, rm, dm, ws=ws, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (pt, dc, rm, dm), ws, o in zip(problems, wss, outs):
+        dpc.dpc_run(pt, dc, rm, dm, ws=ws, out=o)
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t0
+    same = all(torch.equal(b.out[k][f], outs[k][f]) for k in range(0, len(jobs), max(1, len(jobs) // 256))
+               for f in ("rho", "dep", "delta", "label", "ncenters"))
+
+    sum_ops = sum(int(o["rho"].sum().item()) * density_ops(j.d) for o, j in zip(b.out, jobs))
+    dens_ms = prof["density"][1] / max(1, prof["density"][0])
+    achieved = sum_ops / (dens_ms * 1e-3) / 1e12
+    line = {
+        "metric": "points/s batched DPC (rho+delta+labels), 4096 jobs per launch sequence, 1 MI355X",
+        "value": total / batched_s,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": batched_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "batch4096", "jobs": len(jobs), "points": total,
+                   "dims": sorted({j.d for j in jobs}), "n_range": [min(j.n for j in jobs), max(j.n for j in jobs)]},
+        "graph_replay": {"value": total / graph_s, "ms_per_step": graph_s * 1e3},
+        "per_job_launches": {"value": total / single_s, "ms_per_step": single_s * 1e3},
+        "batched_vs_per_job": single_s / batched_s,
+        "batch_equals_per_job": same,
+        "autotune": {str(d): v["options"] for d, v in table.items()},
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in prof.items() if k != "work" and v[0]},
+        "roofline": {"kernel": "density", "avg_ms": dens_ms, "bound": "alu", "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
+    b.close()
+    return 0 if same else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +221,8 @@ def main() -> int:
     ap.add_argument("--workload", default="blobs_1m_d2")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jobs", type=int, default=4096, help="jobs of the batch4096 workload")
+    ap.add_argument("--no-autotune", action="store_true", help="batch4096: library defaults for every job")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy kernel of known size, "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -116,7 +233,8 @@ def main() -> int:
                                    "note, not an implementation", "n_gpus": args.gpus}))
         return 2
 
-    import numpy as np
+    batch_jobs = make_batch_jobs(args.jobs) if args.workload == "batch4096" else None
+
     import torch
 
     from paper_2207_04649_amd import dpc, inputs
@@ -124,6 +242,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         return 1
+    if batch_jobs is not None:
+        return bench_batch(args, batch_jobs)
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
