@@ -114,6 +114,76 @@ def make_batch_jobs(count: int):
         return list(ex.map(_make_job, specs, chunksize=16))
 
 
+def make_serve_requests(duration: float):
+    """Requests of the served workload's trace; new jobs drawn in a process pool (before any GPU use)."""
+    import concurrent.futures as cf
+
+    from paper_2207_04649_amd import inputs, serve
+
+    trace = inputs.serve_trace(duration=duration)
+    specs = [r.spec for r in trace if r.kind == "new"]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(workers) as ex:
+        jobs = dict(zip((sp.seed for sp in specs), ex.map(_make_job, specs, chunksize=4)))
+    return serve.trace_requests(trace, lambda spec: jobs[spec.seed])
+
+
+def bench_serve(args, reqs) -> int:
+    """Replay the Poisson trace in real time through the continuous-batching
+    server; the same trace through one slot without grouping for comparison."""
+    import copy
+
+    import torch
+
+    from paper_2207_04649_amd import dpc, inputs, serve
+
+    warm = inputs.blob_job(1, 5000, 3, 5, 500.0, 4000.0, 0.05)  # module load and first launches
+    t = torch.from_numpy(warm.pts).cuda()
+    dpc.dpc_run(t, warm.d_cut, warm.rho_min, warm.delta_min)
+    torch.cuda.synchronize()
+    results = {}
+    for name, slots, group in (("continuous", args.slots, True), ("one_slot_fifo", 1, False)):
+        rq = [copy.copy(q) for q in reqs]
+        srv = serve.Server(budget_bytes=64 << 30, slots=slots, group_small=group)
+        t0 = time.perf_counter()
+        srv.run(rq)
+        wall = time.perf_counter() - t0
+        done = [q for q in rq if not q.dropped]
+        results[name] = {"latency": serve.latency_summary(rq), "wall_s": wall,
+                         "requests_per_s": len(done) / wall,
+                         "new_points_per_s": sum(q.pts.shape[0] for q in done if q.kind == "new") / wall,
+                         "stats": dict(srv.stats), "peak_hbm_gb": srv.peak_used / 2 ** 30}
+        print(f"{name}: {json.dumps(results[name])}", file=sys.stderr, flush=True)
+    main_r = results["continuous"]
+    line = {
+        "metric": "served DPC latency, arrival -> labels in pinned host memory (p99 of new jobs), 1 MI355X",
+        "value": main_r["latency"]["new"]["p99_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": main_r["wall_s"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "serve", "duration_s": args.duration, "rate_per_s": 200.0,
+                   "requests": len(reqs), "new": sum(1 for q in reqs if q.kind == "new"),
+                   "rethreshold": sum(1 for q in reqs if q.kind == "rethreshold"), "slots": args.slots,
+                   "hbm_budget_gb": 64},
+        "latency": main_r["latency"],
+        "requests_per_s": main_r["requests_per_s"],
+        "new_points_per_s": main_r["new_points_per_s"],
+        "stats": main_r["stats"],
+        "peak_hbm_gb": main_r["peak_hbm_gb"],
+        "one_slot_fifo": {"latency": results["one_slot_fifo"]["latency"],
+                          "requests_per_s": results["one_slot_fifo"]["requests_per_s"]},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def bench_batch(args, jobs) -> int:
     """Many-job batch: all jobs through dpc_batch_run (one launch per phase and
     dimension), against the same jobs launched one dpc_run at a time."""
@@ -223,6 +293,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jobs", type=int, default=4096, help="jobs of the batch4096 workload")
     ap.add_argument("--no-autotune", action="store_true", help="batch4096: library defaults for every job")
+    ap.add_argument("--duration", type=float, default=5.0, help="serve: seconds of the Poisson trace")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent slots (streams)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy kernel of known size, "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -234,6 +306,7 @@ def main() -> int:
         return 2
 
     batch_jobs = make_batch_jobs(args.jobs) if args.workload == "batch4096" else None
+    serve_reqs = make_serve_requests(args.duration) if args.workload == "serve" else None
 
     import torch
 
@@ -244,6 +317,8 @@ def main() -> int:
         return 1
     if batch_jobs is not None:
         return bench_batch(args, batch_jobs)
+    if serve_reqs is not None:
+        return bench_serve(args, serve_reqs)
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
