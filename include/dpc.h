@@ -125,6 +125,7 @@ typedef struct {
   int64_t workspace_bytes;
   int64_t window_radius; /* K0 cells: K0 * L >= floor(sqrt(R - 1)), so (2 K0 + 1)^d cells hold a d_cut-ball */
   int64_t stages;        /* dependent-search stages */
+  int64_t grid_dims;     /* coordinates the cells index (the first grid_dims of d) */
 } dpc_plan_info;
 dpc_status dpc_plan(int64_t n, int32_t d, double d_cut, dpc_plan_info *out);
 
@@ -147,7 +148,7 @@ dpc_status dpc_sync_status(void *ws, void *stream);
 
 /* Plan options of one problem (0 in any field: the library's default).  The defaults
  * also take overrides from the environment (DPC_SUBDIV, DPC_STRIP_CELLS, DPC_STAGES
- * "K:group,...", DPC_RING_CAP) for tuning experiments; explicit options win. */
+ * "K:group,...", DPC_RING_CAP, DPC_GRID_DIMS) for tuning experiments; explicit options win. */
 typedef struct {
   int32_t subdiv;          /* cells per cut-off distance along each axis (1..16) */
   int32_t strip_cells;     /* narrower task strips (cells along the last axis) */
@@ -155,6 +156,8 @@ typedef struct {
   int32_t stage_radius[4]; /* window radius of each stage in cells (1..64) */
   int32_t stage_group[4];  /* tasks whose open points one wave gathers (1..64) */
   int32_t ring_cap;        /* most ring-search steps per point before the prefix scan */
+  int32_t grid_dims;       /* coordinates the cells index (default min(d, 3); d if larger):
+                              the windows cover those, distances always use all d */
 } dpc_tuning;
 
 /* dpc_plan with explicit options (tuning may be NULL). */

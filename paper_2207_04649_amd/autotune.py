@@ -22,9 +22,12 @@ CANDIDATES = [
     {"subdiv": 3},
     {"stages": [(1, 1)]},
     {"stages": [(1, 1), (2, 4)]},
-    {"stages": [(2, 1)]},
     {"strip_cells": 16},
     {"subdiv": 2, "stages": [(1, 1)]},
+    {"grid_dims": 2},
+    {"grid_dims": 2, "subdiv": 4},
+    {"grid_dims": 8},                      # every coordinate indexed
+    {"grid_dims": 8, "stages": [(1, 1)]},
 ]
 
 

@@ -120,8 +120,8 @@ int64_t p16_extent(int d) {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Cells per ball half-extent for each dimension (finer cells clip the windows
-// closer to the d_cut-ball; the table grows as their d-th power).
+// Cells per cut-off distance for each number of grid dimensions (finer cells
+// clip the windows closer to the d_cut-ball; the table grows as their power).
 int default_subdivision(int d) { return d <= 2 ? 4 : (d == 3 ? 2 : 1); }
 
 // Options from the environment (tuning experiments); 0 = not set.
@@ -131,6 +131,7 @@ dpc_tuning env_tuning() {
   if (const char *env = std::getenv("DPC_SUBDIV")) t.subdiv = std::atoi(env);
   if (const char *env = std::getenv("DPC_STRIP_CELLS")) t.strip_cells = std::atoi(env);
   if (const char *env = std::getenv("DPC_RING_CAP")) t.ring_cap = std::atoi(env);
+  if (const char *env = std::getenv("DPC_GRID_DIMS")) t.grid_dims = std::atoi(env);
   if (const char *env = std::getenv("DPC_STAGES")) {  // "K:group,K:group,..."
     int k = 0;
     for (const char *c = env; *c && k < 4;) {
@@ -179,12 +180,25 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   if (L0 < 1) L0 = 1;
   if (L0 > DPC_COORD_LIMIT) L0 = DPC_COORD_LIMIT;
   p.L0 = int32_t(L0);
-  int S = default_subdivision(d);
+  // Grid dimensions: the first gm coordinates are indexed.  In many dimensions a
+  // full grid leaves most rows with a point or two, so tasks run nearly empty
+  // waves and windows and rings grow as 3^(d-1); past four dimensions three
+  // indexed ones keep rows full (measured on blob and random-walk data).
+  int gm = d <= 4 ? d : 3;
+  {
+    const int v = pick(opt ? opt->grid_dims : 0, env.grid_dims);
+    if (v >= 1) gm = v < d ? v : d;  // more than d: all of them
+  }
+  p.gm = gm;
+  // A partial grid runs the exact int64 distance path with cells one cut-off
+  // wide; a full one subdivides the cut-off (finer cells clip windows closer to
+  // the ball, the table grows as their power).
+  int S = gm < d ? 1 : default_subdivision(gm);
   {
     const int v = pick(opt ? opt->subdiv : 0, env.subdiv);
     if (v >= 1 && v <= 16) S = v;
   }
-  const int64_t nc_max = iroot(table_cap(n), d);
+  const int64_t nc_max = iroot(table_cap(n), gm);
   int64_t L = 1, nc = 1;
   for (;; --S) {
     L = (L0 + S - 1) / S;
@@ -204,13 +218,19 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   const int64_t E = p16_extent(d);
   auto p16_ok = [&](int64_t K, int64_t wc) { return wc >= 1 && (wc + 2 * K) * L <= E && (2 * K + 1) * L <= E; };
   const int64_t wc16 = E / L - 2 * int64_t(p.K0);
-  if (p16_ok(p.K0, wc16)) {
+  // The packed path needs every coordinate difference bounded by the window,
+  // so every coordinate must be indexed.
+  if (gm == d && p16_ok(p.K0, wc16)) {
     p.mode = kModeP16;
     p.wc = int32_t(wc16 < nc ? wc16 : nc);
   } else {
     p.mode = kModeI64;
     p.wc = int32_t(nc);
   }
+  // Without the packed path's width limit, a strip spans a whole row, and
+  // tasks of sparse rows spread over many cells; four-cell strips keep each
+  // task's window narrow.
+  if (gm < d && p.wc > 4) p.wc = 4;
   {
     const int64_t v = pick(opt ? opt->strip_cells : 0, env.strip_cells);
     if (v >= 1 && v < p.wc) p.wc = int32_t(v);  // narrower only
@@ -235,21 +255,23 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   for (int k = 0; k < st.nstages; ++k) {
     const int K = st.stage_radius[k];
     int64_t rows = 1;
-    for (int t = 0; t < d - 1; ++t) rows *= 2 * K + 1;
+    for (int t = 0; t < gm - 1; ++t) rows *= 2 * K + 1;
     if (k > 0 && rows > 4096) break;
     p.stageK[p.nstages] = K;
     p.stageGroup[p.nstages] = st.stage_group[k];
-    p.stageMode[p.nstages] = p16_ok(K, p.wc) ? kModeP16 : kModeI64;
+    p.stageMode[p.nstages] = (gm == d && p16_ok(K, p.wc)) ? kModeP16 : kModeI64;
     ++p.nstages;
   }
-  p.ring_cap = kRingCostCap;
+  // Ring steps before the prefix scan: more in more dimensions, where rings
+  // stay cheap longer than scanning a long density prefix.
+  p.ring_cap = d <= 2 ? kRingCostCap : 4 * kRingCostCap;
   {
     const int v = pick(opt ? opt->ring_cap : 0, env.ring_cap);
     if (v >= 1 && v <= 1 << 20) p.ring_cap = v;
   }
   p.nsx = int32_t((nc + p.wc - 1) / p.wc);
-  p.ncells = ipow(nc, d);
-  p.nrows = ipow(nc, d - 1);
+  p.ncells = ipow(nc, gm);
+  p.nrows = ipow(nc, gm - 1);
   p.nstrips = p.nrows * p.nsx;
   p.max_tasks = n / kQueryChunk + p.nstrips + 1;
 
@@ -364,6 +386,7 @@ void fill_plan_info(const Plan &p, dpc_plan_info *out) {
   out->workspace_bytes = int64_t(p.total);
   out->window_radius = p.K0;
   out->stages = p.nstages;
+  out->grid_dims = p.gm;
 }
 
 dpc_status check_job(const dpc_job &j) {

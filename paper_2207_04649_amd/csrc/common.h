@@ -53,7 +53,7 @@ struct Plan {
   int32_t K0;        // density window radius in cells: K0 * L >= L0
   int32_t L;         // cell side
   int32_t nc;        // cells per dimension
-  int32_t wc;        // strip width in cells along the last dimension
+  int32_t wc;        // strip width in cells along the last grid dimension
   int32_t nsx;       // strips per row, ceil(nc / wc)
   int32_t mode;      // DistMode of the density kernel
   int32_t nstages;   // dependent-search stages
@@ -61,8 +61,10 @@ struct Plan {
   int32_t stageGroup[4]; // tasks gathered per wave in each stage
   int32_t stageMode[4];  // DistMode of each stage
   int32_t ring_cap;  // most ring-search steps per point before the prefix scan
-  int64_t ncells;    // nc^d
-  int64_t nrows;     // nc^(d-1)
+  int32_t gm;        // grid dimensions: the cells index the first gm coordinates (1..d)
+  int32_t pad1;
+  int64_t ncells;    // nc^gm
+  int64_t nrows;     // nc^(gm-1)
   int64_t nstrips;   // nrows * nsx
   int64_t max_tasks;
   // workspace byte offsets

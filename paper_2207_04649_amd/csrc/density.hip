@@ -24,8 +24,7 @@ __device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w
   const int32_t negR = -int32_t(p.R < INT32_MAX ? p.R : INT32_MAX);
   const int K = p.K0;
   const uint64_t clip2 = uint64_t(p.R - 1);  // D2 <= R - 1 is inside the ball
-  int nrow = 1;
-  for (int t = 0; t < D - 1; ++t) nrow *= 2 * K + 1;
+  const int nrow = int(window_rows(p, K));
 
   const uint32_t nw = grid_waves(blk);
   for (uint32_t t = wave_index(blk); t < ntasks; t += nw) {
@@ -37,7 +36,7 @@ __device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w
     int32_t qx[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) qx[k] = w.spts[int64_t(q) * D + k];
-    task_span<D>(p, g, qx[D - 1], true);
+    task_span<D>(p, g, w.spts[int64_t(q) * D + (p.gm - 1)], true);  // strip-dimension coordinate
     uint32_t qk[W];
     if (MODE == kModeP16) {
 #pragma unroll

@@ -44,7 +44,7 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int K, 
   int32_t qx[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) qx[k] = w.spts[int64_t(q) * D + k];
-  task_span<D>(p, g, qx[D - 1], valid);
+  task_span<D>(p, g, w.spts[int64_t(q) * D + (p.gm - 1)], valid);  // strip-dimension coordinate
   const uint64_t Ki = w.sK[q];
   const uint32_t id = uint32_t(~uint32_t(Ki));
   uint64_t best = first ? kNoKey : w.best[id];
@@ -59,8 +59,7 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int K, 
     // inner-loop key: (D2 << 32) | id, D2 < 2^31 on this path
     if (best != kNoKey) best = ((best >> kIdBits) << 32) | (best & kIdMask);
   }
-  int nrow = 1;
-  for (int t = 0; t < D - 1; ++t) nrow *= 2 * K + 1;
+  const int nrow = int(window_rows(p, K));
   for (int rb = 0; rb < nrow; rb += kWave) {
     uint32_t sb = 0, se = 0;
     if (rb + lane < nrow) window_row<D>(p, g, K, rb + lane, clip2, w.cnt, &sb, &se);
@@ -278,6 +277,7 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
       x[k] = uniform(spc[int64_t(q) * D + k]);
       c[k] = x[k] / p.L;
     }
+    const int32_t xs = uniform(spc[int64_t(q) * D + (p.gm - 1)]);  // coordinate along the strip dimension
     const uint64_t Ki = uniform(sKc[q]);
     const uint32_t id = uint32_t(~uint32_t(Ki));
     const int64_t rho = int64_t(Ki >> 32);
@@ -292,7 +292,7 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
       const int32_t k1 = 2 * k0;
       const int64_t side = 2 * int64_t(k1) + 1;
       int64_t nrows = 1;
-      for (int t = 0; t < D - 1; ++t) nrows *= side;
+      for (int t = 0; t < p.gm - 1; ++t) nrows *= side;
       const uint64_t bestd2 = best >> kIdBits;  // huge when there is no best yet
       for (int64_t rb = 0; rb < nrows; rb += kWave) {
         uint32_t b1 = 0, n1 = 0, b2 = 0, n2 = 0;
@@ -302,23 +302,25 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
           bool ok = true, outer = false;
 #pragma unroll
           for (int t = 0; t < D - 1; ++t) {
-            const int32_t o = int32_t(r % side) - k1;
-            r /= side;
-            const int32_t nb = c[t] + o;
-            ok = ok && nb >= 0 && nb < p.nc;
-            outer = outer || o > k0 || o < -k0;
-            rowk = rowk * p.nc + nb;
-            const int64_t gp = gap_to(x[t], int64_t(nb) * p.L, int64_t(nb + 1) * p.L - 1);
-            md += gp * gp;
+            if (t < p.gm - 1) {
+              const int32_t o = int32_t(r % side) - k1;
+              r /= side;
+              const int32_t nb = c[t] + o;
+              ok = ok && nb >= 0 && nb < p.nc;
+              outer = outer || o > k0 || o < -k0;
+              rowk = rowk * p.nc + nb;
+              const int64_t gp = gap_to(x[t], int64_t(nb) * p.L, int64_t(nb + 1) * p.L - 1);
+              md += gp * gp;
+            }
           }
           if (ok && uint64_t(md) <= bestd2) {
-            // last-dimension cells that can hold a point within the best distance
-            const int32_t cl = c[D - 1];
+            // strip-dimension cells that can hold a point within the best distance
+            const int32_t cl = xs / p.L;
             int32_t lo = max(cl - k1, 0), hi = min(cl + k1, p.nc - 1);
             if (bestd2 < (uint64_t(1) << 38)) {
               const int64_t rr = isqrt_floor(bestd2 - uint64_t(md));
-              lo = max(lo, int32_t(max(int64_t(x[D - 1]) - rr, int64_t(0)) / p.L));
-              hi = min(hi, int32_t(min(int64_t(x[D - 1]) + rr, int64_t(DPC_COORD_LIMIT - 1)) / p.L));
+              lo = max(lo, int32_t(max(int64_t(xs) - rr, int64_t(0)) / p.L));
+              hi = min(hi, int32_t(min(int64_t(xs) + rr, int64_t(DPC_COORD_LIMIT - 1)) / p.L));
             }
             const int64_t base = rowk * p.nc;
             if (outer) {  // the whole row lies outside the block searched so far
@@ -381,12 +383,15 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
         defer = true;
         break;
       }
-      // The searched block is now every cell within k1 of the point's cell.
+      // The searched block is now every cell within k1 of the point's cell (in
+      // the grid dimensions; a gap in one of them bounds the full distance).
       int64_t gap = INT64_MAX;
 #pragma unroll
       for (int t = 0; t < D; ++t) {
-        if (c[t] - k1 >= 1) gap = min(gap, int64_t(x[t]) - int64_t(c[t] - k1) * p.L + 1);
-        if (c[t] + k1 <= p.nc - 2) gap = min(gap, int64_t(c[t] + k1 + 1) * p.L - int64_t(x[t]));
+        if (t < p.gm) {
+          if (c[t] - k1 >= 1) gap = min(gap, int64_t(x[t]) - int64_t(c[t] - k1) * p.L + 1);
+          if (c[t] + k1 <= p.nc - 2) gap = min(gap, int64_t(c[t] + k1 + 1) * p.L - int64_t(x[t]));
+        }
       }
       if (gap == INT64_MAX) break;  // the block covers the whole grid
       if (best != kNoKey && (best >> kIdBits) < uint64_t(gap) * uint64_t(gap)) break;

@@ -102,8 +102,8 @@ __device__ __forceinline__ void scan_add(Blk k, uint32_t *data, int64_t count, c
   }
 }
 
-// Cell key of every point (row-major over the cell coordinates, last dimension
-// fastest) and its slot in the cell.  Out-of-range coordinates are clamped and flagged.
+// Cell key of every point (row-major over the cell coordinates of its first gm
+// coordinates, the last of them fastest) and its slot in the cell.  Out-of-range coordinates are clamped and flagged.
 __device__ __forceinline__ void cell_keys(Blk k, const int32_t *__restrict__ pts, const Plan &p,
                                           uint32_t *__restrict__ cnt, uint32_t *__restrict__ key,
                                           uint32_t *__restrict__ slot, DevHeader *__restrict__ hdr) {
@@ -116,7 +116,7 @@ __device__ __forceinline__ void cell_keys(Blk k, const int32_t *__restrict__ pts
         bad = true;
         x = x < 0 ? 0 : DPC_COORD_LIMIT - 1;
       }
-      kk = kk * uint32_t(p.nc) + uint32_t(x / p.L);
+      if (t < p.gm) kk = kk * uint32_t(p.nc) + uint32_t(x / p.L);
     }
     if (bad) atomicOr(&hdr->status, 1u);
     key[i] = kk;

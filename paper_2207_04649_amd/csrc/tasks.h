@@ -1,17 +1,26 @@
 // Task geometry shared by the density and dependent-search kernels.
 //
-// A task is up to 64 cell-order points of one strip (cells of one row of the
-// grid, all coordinates but the last fixed).  Its search window of radius K
-// cells is, in every row within K of the task's row ((2K+1)^(d-1) rows), the
-// contiguous cell range [x0 - K, x1 + K], where x0..x1 are the last-dimension
-// cells of the task's points.  Cells are keyed row-major, so each row range is
-// one contiguous run of the cell-ordered arrays.
+// The cells index the first gm coordinates of a point (gm <= d, a plan value);
+// a row fixes the first gm - 1 cell coordinates, and a strip is a run of cells
+// of one row along grid dimension gm - 1.  A task is up to 64 cell-order points
+// of one strip.  Its search window of radius K cells is, in every row within K
+// of the task's row ((2K+1)^(gm-1) rows), the contiguous cell range
+// [x0 - K, x1 + K], where x0..x1 are the cells of the task's points along the
+// strip dimension.  Cells are keyed row-major, so each row range is one
+// contiguous run of the cell-ordered arrays.  Coordinates past gm are not
+// indexed: the projection onto the grid dimensions never increases a distance,
+// so the windows still hold every point they must, and distances are always
+// computed over all d coordinates.
 //
 // Rows and row ranges are clipped to a radius when one is known: a row whose
 // nearest coordinate is farther than the radius from the task's row is
 // skipped, and the cell range is cut to the cells within the radius of the
-// task's last-coordinate span.  With the cut-off distance as the radius (local
-// density, Def. 1) the window follows the d_cut-ball instead of its bounding box.
+// task's span along the strip dimension.  With the cut-off distance as the
+// radius (local density, Def. 1) the window follows the d_cut-ball instead of
+// its bounding box.
+//
+// Loops over grid dimensions run over all D - 1 (or D) indices, fully
+// unrolled, with a guard on gm, so register arrays are indexed by constants.
 #pragma once
 
 #include "common.h"
@@ -20,9 +29,9 @@ namespace dpc {
 
 template <int D>
 struct TaskGeom {
-  int32_t c[D > 1 ? D - 1 : 1];  // cell coordinates of the task's row
-  int32_t x0, x1;                // last-dimension cells of the task's points
-  int32_t xlo, xhi;              // last-dimension coordinate span of the task's points
+  int32_t c[D > 1 ? D - 1 : 1];  // cell coordinates of the task's row (first gm - 1 used)
+  int32_t x0, x1;                // strip-dimension cells of the task's points
+  int32_t xlo, xhi;              // strip-dimension coordinate span of the task's points
 };
 
 // Row coordinates of strip `strip`.
@@ -31,8 +40,11 @@ __device__ __forceinline__ void strip_row(const Plan &p, uint32_t strip, TaskGeo
   int64_t row = int64_t(strip) / p.nsx;
 #pragma unroll
   for (int t = D - 2; t >= 0; --t) {
-    g.c[t] = int32_t(row % p.nc);
-    row /= p.nc;
+    g.c[t] = 0;
+    if (t < p.gm - 1) {
+      g.c[t] = int32_t(row % p.nc);
+      row /= p.nc;
+    }
   }
 }
 
@@ -43,6 +55,13 @@ __device__ __forceinline__ int64_t row_gap(int32_t o, int32_t L) {
   return a == 0 ? 0 : int64_t(a - 1) * L + 1;
 }
 
+// Rows of a window of radius K: (2K+1)^(gm-1).
+__device__ __forceinline__ int64_t window_rows(const Plan &p, int K) {
+  int64_t r = 1;
+  for (int t = 0; t < p.gm - 1; ++t) r *= 2 * K + 1;
+  return r;
+}
+
 // Largest r with r * r <= v (v < 2^62).
 __device__ __forceinline__ int64_t isqrt_floor(uint64_t v) {
   int64_t r = int64_t(__builtin_sqrt(double(v)));
@@ -51,7 +70,7 @@ __device__ __forceinline__ int64_t isqrt_floor(uint64_t v) {
   return r;
 }
 
-// Candidate range [b, e) of row r (0 <= r < (2K+1)^(D-1)) of the window of
+// Candidate range [b, e) of row r (0 <= r < window_rows(p, K)) of the window of
 // radius K, clipped to squared radius `clip2` (no clipping when clip2 is
 // UINT64_MAX).  Empty if the row is outside the grid or beyond the radius.
 template <int D>
@@ -64,13 +83,15 @@ __device__ __forceinline__ void window_row(const Plan &p, const TaskGeom<D> &g, 
   const int side = 2 * K + 1;
 #pragma unroll
   for (int t = 0; t < D - 1; ++t) {
-    const int32_t o = r % side - K;
-    r /= side;
-    const int32_t nb = g.c[t] + o;
-    ok = ok && nb >= 0 && nb < p.nc;
-    rowk = rowk * p.nc + nb;
-    const int64_t gy = row_gap(o, p.L);
-    dy2 += gy * gy;
+    if (t < p.gm - 1) {
+      const int32_t o = r % side - K;
+      r /= side;
+      const int32_t nb = g.c[t] + o;
+      ok = ok && nb >= 0 && nb < p.nc;
+      rowk = rowk * p.nc + nb;
+      const int64_t gy = row_gap(o, p.L);
+      dy2 += gy * gy;
+    }
   }
   if (!ok) return;
   int32_t lo = max(g.x0 - K, 0), hi = min(g.x1 + K, p.nc - 1);
@@ -86,17 +107,21 @@ __device__ __forceinline__ void window_row(const Plan &p, const TaskGeom<D> &g, 
 }
 
 // Squared distance from a point to the outside of the unclipped window of
-// radius K: every point outside has D2 >= the returned value (UINT64_MAX when
-// the window reaches the grid boundary on every side).
+// radius K: every point outside has D2 >= the returned value, since its gap in
+// one grid dimension alone is that large (UINT64_MAX when the window reaches the
+// grid boundary on every side).
 template <int D>
 __device__ __forceinline__ uint64_t window_exterior_d2(const Plan &p, const TaskGeom<D> &g, int K, const int32_t *x) {
   int64_t gap = INT64_MAX;
 #pragma unroll
   for (int t = 0; t < D; ++t) {
-    const int32_t lo = (t == D - 1) ? g.x0 - K : g.c[t] - K;
-    const int32_t hi = (t == D - 1) ? g.x1 + K : g.c[t] + K;
-    if (lo >= 1) gap = min(gap, int64_t(x[t]) - int64_t(lo) * p.L + 1);
-    if (hi <= p.nc - 2) gap = min(gap, int64_t(hi + 1) * p.L - int64_t(x[t]));
+    if (t < p.gm) {
+      const bool last = t == p.gm - 1;
+      const int32_t lo = last ? g.x0 - K : g.c[t < D - 1 ? t : 0] - K;
+      const int32_t hi = last ? g.x1 + K : g.c[t < D - 1 ? t : 0] + K;
+      if (lo >= 1) gap = min(gap, int64_t(x[t]) - int64_t(lo) * p.L + 1);
+      if (hi <= p.nc - 2) gap = min(gap, int64_t(hi + 1) * p.L - int64_t(x[t]));
+    }
   }
   return gap == INT64_MAX ? ~uint64_t(0) : uint64_t(gap) * uint64_t(gap);
 }
@@ -127,8 +152,8 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
-// Finish a task's geometry from its points' last coordinates (lanes holding a
-// valid point pass valid = true; all 64 lanes call this).
+// Finish a task's geometry from its points' strip-dimension coordinates (lanes
+// holding a valid point pass valid = true; all 64 lanes call this).
 template <int D>
 __device__ __forceinline__ void task_span(const Plan &p, TaskGeom<D> &g, int32_t xlast, bool valid) {
   g.xlo = uniform(wave_min_i32(valid ? xlast : INT32_MAX));

@@ -58,8 +58,11 @@ def test_plan_invariants(n, d, d_cut):
     L, K0 = p["cell_side"], p["window_radius"]
     assert K0 * L >= min(max(1, math.isqrt(R - 1)), dpc.COORD_LIMIT), "(2 K0 + 1)^d cells must hold the d_cut-ball"
     assert p["cells_per_dim"] * L >= dpc.COORD_LIMIT
-    assert p["cells"] == p["cells_per_dim"] ** d <= min(1 << 26, max(4096, 8 * n))
-    if p["mode"] == 0:  # packed 16-bit path: window extent keeps |dx| < 2^15 and D2 < 2^31
+    gm = p["grid_dims"]
+    assert 1 <= gm <= d
+    assert p["cells"] == p["cells_per_dim"] ** gm <= min(1 << 26, max(4096, 8 * n))
+    if p["mode"] == 0:  # packed 16-bit path: every coordinate indexed, |dx| < 2^15 and D2 < 2^31
+        assert gm == d
         E = (p["strip_cells"] + 2 * K0) * L
         assert E - 1 <= 32767 and d * (E - 1) ** 2 <= 2 ** 31 - 1
     assert p["stages"] >= 1
