@@ -122,7 +122,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 // Cells per cut-off distance for each number of grid dimensions (finer cells
 // clip the windows closer to the d_cut-ball; the table grows as their power).
-int default_subdivision(int d) { return d <= 2 ? 4 : (d == 3 ? 2 : 1); }
+int default_subdivision(int d) { return d <= 3 ? 2 : 1; }
 
 // Options from the environment (tuning experiments); 0 = not set.
 dpc_tuning env_tuning() {
@@ -240,11 +240,9 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   // has more than 4096 rows.
   dpc_tuning st;
   std::memset(&st, 0, sizeof(st));
-  st.nstages = 2;
+  st.nstages = 1;  // one window stage, then the ring search (measured best on 2-D to 6-D data)
   st.stage_radius[0] = 1;
   st.stage_group[0] = 1;
-  st.stage_radius[1] = 3;
-  st.stage_group[1] = 4;
   if (opt && opt->nstages) {
     if (!valid_stages(*opt)) return false;
     st = *opt;
