@@ -148,7 +148,8 @@ dpc_status dpc_sync_status(void *ws, void *stream);
 
 /* Plan options of one problem (0 in any field: the library's default).  The defaults
  * also take overrides from the environment (DPC_SUBDIV, DPC_STRIP_CELLS, DPC_STAGES
- * "K:group,...", DPC_RING_CAP, DPC_GRID_DIMS) for tuning experiments; explicit options win. */
+ * "K:group,...", DPC_RING_CAP, DPC_GRID_DIMS, DPC_ROW_SPLIT) for tuning experiments; explicit
+ * options win. */
 typedef struct {
   int32_t subdiv;          /* cells per cut-off distance along each axis (1..16) */
   int32_t strip_cells;     /* narrower task strips (cells along the last axis) */
@@ -156,8 +157,9 @@ typedef struct {
   int32_t stage_radius[4]; /* window radius of each stage in cells (1..64) */
   int32_t stage_group[4];  /* tasks whose open points one wave gathers (1..64) */
   int32_t ring_cap;        /* most ring-search steps per point before the prefix scan */
-  int32_t grid_dims;       /* coordinates the cells index (default min(d, 3); d if larger):
-                              the windows cover those, distances always use all d */
+  int32_t grid_dims;       /* coordinates the cells index (default d up to 4, else 3; d if
+                              larger): the windows cover those, distances always use all d */
+  int32_t row_split;       /* density work units per task (1..window rows): parts of its rows */
 } dpc_tuning;
 
 /* dpc_plan with explicit options (tuning may be NULL). */

@@ -132,6 +132,7 @@ dpc_tuning env_tuning() {
   if (const char *env = std::getenv("DPC_STRIP_CELLS")) t.strip_cells = std::atoi(env);
   if (const char *env = std::getenv("DPC_RING_CAP")) t.ring_cap = std::atoi(env);
   if (const char *env = std::getenv("DPC_GRID_DIMS")) t.grid_dims = std::atoi(env);
+  if (const char *env = std::getenv("DPC_ROW_SPLIT")) t.row_split = std::atoi(env);
   if (const char *env = std::getenv("DPC_STAGES")) {  // "K:group,K:group,..."
     int k = 0;
     for (const char *c = env; *c && k < 4;) {
@@ -266,6 +267,16 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   {
     const int v = pick(opt ? opt->ring_cap : 0, env.ring_cap);
     if (v >= 1 && v <= 1 << 20) p.ring_cap = v;
+  }
+  // Density work units per task: by default the whole window (splitting it by
+  // rows balances the waves better, but its atomic adds and repeated task
+  // set-up cost more than they save on the measured workloads).
+  {
+    int64_t rows = 1;
+    for (int t = 0; t < gm - 1; ++t) rows *= 2 * p.K0 + 1;
+    p.row_split = 1;
+    const int v = pick(opt ? opt->row_split : 0, env.row_split);
+    if (v >= 1) p.row_split = int32_t(std::min<int64_t>(v, rows));
   }
   p.nsx = int32_t((nc + p.wc - 1) / p.wc);
   p.ncells = ipow(nc, gm);
@@ -525,7 +536,8 @@ dpc_status dpc_batch_plan(const dpc_job *jobs, int32_t njobs, const dpc_tuning *
     add_blocks(b->maps[kMapCells], uint32_t(k), (p.ncells + kBatchCells) / kBatchCells);
     add_blocks(b->maps[kMapStrips], uint32_t(k), (p.nstrips + kBatchPoints) / kBatchPoints);
     const uint32_t w0 = uint32_t(b->maps[kMapWork].vjob.size());
-    add_blocks(b->maps[kMapWork], uint32_t(k), std::min<int64_t>(2048, (p.max_tasks + kBatchTasks - 1) / kBatchTasks));
+    add_blocks(b->maps[kMapWork], uint32_t(k),
+               std::min<int64_t>(2048, (p.max_tasks * p.row_split + kBatchTasks - 1) / kBatchTasks));
     if (b->ngroups == 0 || b->gdim[b->ngroups - 1] != p.d) {
       b->gdim[b->ngroups] = p.d;
       b->gwork0[b->ngroups] = w0;

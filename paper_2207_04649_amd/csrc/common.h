@@ -62,7 +62,7 @@ struct Plan {
   int32_t stageMode[4];  // DistMode of each stage
   int32_t ring_cap;  // most ring-search steps per point before the prefix scan
   int32_t gm;        // grid dimensions: the cells index the first gm coordinates (1..d)
-  int32_t pad1;
+  int32_t row_split; // density work units per task: its window rows in this many parts
   int64_t ncells;    // nc^gm
   int64_t nrows;     // nc^(gm-1)
   int64_t nstrips;   // nrows * nsx

@@ -5,9 +5,15 @@
 // within K0 of the task's cells (K0 * L >= floor(sqrt(R - 1)), so it covers every
 // d_cut-ball) and is clipped to the balls' union row by row.  The wave walks its
 // candidate runs with scalar loads, so every candidate reaches all 64 lanes as a
-// scalar operand: no LDS, no barriers.  Waves take tasks in a static interleave
-// (see wave_index); the paper balances the per-point range searches with dynamic
-// OpenMP scheduling (Section 3), the interleave does it in wave-sized units.
+// scalar operand: no LDS, no barriers.
+//
+// Work units are (task, part of its window rows): a dense task's window holds
+// thousands of candidates, so whole tasks leave a few waves with several times
+// the average work.  With more than one part per task, every part adds its
+// counts into rho with an atomic add (rho cleared first); with one, the count is
+// stored.  Waves take units in a static interleave (see wave_index); the paper
+// balances the per-point range searches with dynamic OpenMP scheduling
+// (Section 3), the interleave does it in these smaller units.
 #include "tasks.h"
 
 namespace dpc {
@@ -26,8 +32,15 @@ __device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w
   const uint64_t clip2 = uint64_t(p.R - 1);  // D2 <= R - 1 is inside the ball
   const int nrow = int(window_rows(p, K));
 
+  const uint32_t parts = uint32_t(p.row_split);
+  const int rows_per = (nrow + int(parts) - 1) / int(parts);
+  const uint64_t units = uint64_t(ntasks) * parts;
+
   const uint32_t nw = grid_waves(blk);
-  for (uint32_t t = wave_index(blk); t < ntasks; t += nw) {
+  for (uint64_t u = wave_index(blk); u < units; u += nw) {
+    const uint32_t t = uint32_t(u / parts);
+    const int r_lo = int(u % parts) * rows_per;
+    const int r_hi = min(nrow, r_lo + rows_per);
     const uint32_t qb = uniform(uint32_t(tc[4 * int64_t(t)]));
     const uint32_t qe = uniform(uint32_t(tc[4 * int64_t(t) + 1]));
     TaskGeom<D> g;
@@ -43,15 +56,18 @@ __device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w
       for (int k = 0; k < W; ++k) qk[k] = w.spk[int64_t(q) * W + k];
     }
     uint32_t count = 0;
-    for (int rb = 0; rb < nrow; rb += kWave) {
+    for (int rb = r_lo; rb < r_hi; rb += kWave) {
       uint32_t sb = 0, se = 0;
-      if (rb + lane < nrow) window_row<D>(p, g, K, rb + lane, clip2, w.cnt, &sb, &se);
-      const int nr = min(kWave, nrow - rb);
+      if (rb + lane < r_hi) window_row<D>(p, g, K, rb + lane, clip2, w.cnt, &sb, &se);
+      const int nr = min(kWave, r_hi - rb);
       for (int r = 0; r < nr; ++r) {
         const uint32_t b = __builtin_amdgcn_readlane(sb, r);
         const uint32_t e = __builtin_amdgcn_readlane(se, r);
         uint32_t j = b;
         if (MODE == kModeP16) {
+          // B candidates per batch: one scalar load per 16 words.  (Double
+          // buffering the loads needs half-size batches for the SGPRs and was
+          // measured slower; 8 resident waves per SIMD hide the latency.)
           constexpr int B = 16 / W;
           for (; j + B <= e; j += B) {
             DPC_CONST(uint32_t) *cb = spk + int64_t(j) * W;
@@ -85,11 +101,30 @@ __device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w
         }
       }
     }
-    // Lanes past the end of the task repeat its last query, so they store the
-    // same values to the same places: no lane-divergent branch in the loop.
+    // Lanes past the end of the task repeat its last query: they store the same
+    // value, or add 0, so no lane-divergent branch surrounds the store.
     const int32_t id = w.sid[q];
-    rho[id] = int32_t(count);
-    w.sK[q] = (uint64_t(count) << 32) | uint32_t(~uint32_t(id));
+    if (parts == 1)
+      rho[id] = int32_t(count);
+    else
+      atomicAdd(&rho[id], qb + uint32_t(lane) < qe ? int32_t(count) : 0);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t *__restrict__ v, int64_t n) {
+  for (int64_t i = thread_index(grid_blk()); i < n; i += grid_threads(grid_blk())) v[i] = 0;
+}
+
+// rho of every job that splits its density tasks, cleared for the atomic adds.
+__global__ __launch_bounds__(kBlock) void kb_zero_rho(const JobDev *jobs, VMap m) {
+  for (uint32_t v = m.v0 + blockIdx.x; v < m.v1; v += gridDim.x) {
+    const uint32_t j = vjob_of(m, v);
+    const Blk k = vblk_of(m, v, j);
+    if (uniform(int32_t(as_const(jobs)[j].p.row_split)) > 1) {
+      const int64_t n = as_const(jobs)[j].p.n;
+      int32_t *rho = as_const(jobs)[j].rho;
+      for (int64_t i = thread_index(k); i < n; i += grid_threads(k)) rho[i] = 0;
+    }
   }
 }
 
@@ -134,7 +169,8 @@ unsigned persistent_blocks(int64_t max_items) {
 }
 
 hipError_t launch_density(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s) {
-  const unsigned blocks = persistent_blocks(p.max_tasks);
+  if (p.row_split > 1) DPC_LAUNCH((k_zero_i32), blocks_for(p.n, kBlock * 4), kBlock, s, rho, p.n);
+  const unsigned blocks = persistent_blocks(p.max_tasks * p.row_split);
   switch (p.d) {
     case 1: return launch_d<1>(p, w, rho, s, blocks);
     case 2: return launch_d<2>(p, w, rho, s, blocks);
@@ -149,6 +185,7 @@ hipError_t launch_density(const Plan &p, const Ws &w, int32_t *rho, hipStream_t 
 }
 
 hipError_t batch_density(const BatchMaps &B, hipStream_t s) {
+  if (vgrid(B.pts)) DPC_LAUNCH((kb_zero_rho), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   for (int g = 0; g < B.ngroups; ++g) {
     VMap m = B.work;
     m.v0 = B.gwork0[g];

@@ -319,8 +319,10 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
             int32_t lo = max(cl - k1, 0), hi = min(cl + k1, p.nc - 1);
             if (bestd2 < (uint64_t(1) << 38)) {
               const int64_t rr = isqrt_floor(bestd2 - uint64_t(md));
-              lo = max(lo, int32_t(max(int64_t(xs) - rr, int64_t(0)) / p.L));
-              hi = min(hi, int32_t(min(int64_t(xs) + rr, int64_t(DPC_COORD_LIMIT - 1)) / p.L));
+              const int32_t a = int32_t(max(int64_t(xs) - rr, int64_t(0)));
+              const int32_t c2 = int32_t(min(int64_t(xs) + rr, int64_t(DPC_COORD_LIMIT - 1)));
+              lo = max(lo, a / p.L);
+              hi = min(hi, c2 / p.L);
             }
             const int64_t base = rowk * p.nc;
             if (outer) {  // the whole row lies outside the block searched so far

@@ -5,8 +5,10 @@
 // itself, Section 2.1).  The dependent point always ranks higher, so the links
 // form a forest whose roots are the centers, and a point's label is its root.
 // The paper propagates labels by depth-first search from the centers (Section
-// 2.2, step 4); here two rounds of in-place pointer jumping shorten the chains
+// 2.2, step 4); here three rounds of in-place pointer jumping shorten the chains
 // and a final pass follows each chain to its root.
+#include <cstdlib>
+
 #include "common.h"
 
 namespace dpc {
@@ -127,8 +129,12 @@ hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const
   DPC_LAUNCH((k_zero_count), 1, kWave, s, nc);
   const unsigned blocks = blocks_for(n, kBlock);
   DPC_LAUNCH((k_label_init), blocks, kBlock, s, n, rho, dep, delta, rho_min, delta_min, label, nc, hdr);
-  DPC_LAUNCH((k_jump), blocks, kBlock, s, n, label);
-  DPC_LAUNCH((k_jump), blocks, kBlock, s, n, label);
+  int jumps = 3;
+  if (const char *env = std::getenv("DPC_LABEL_JUMPS")) {  // tuning override
+    const int v = std::atoi(env);
+    if (v >= 0 && v <= 16) jumps = v;
+  }
+  for (int k = 0; k < jumps; ++k) DPC_LAUNCH((k_jump), blocks, kBlock, s, n, label);
   DPC_LAUNCH((k_root), blocks, kBlock, s, n, label);
   return hipGetLastError();
 }

@@ -98,8 +98,11 @@ __device__ __forceinline__ void window_row(const Plan &p, const TaskGeom<D> &g, 
   if (clip2 != ~uint64_t(0)) {
     if (uint64_t(dy2) > clip2) return;
     const int64_t hw = isqrt_floor(clip2 - uint64_t(dy2));
-    lo = max(lo, int32_t(max(int64_t(g.xlo) - hw, int64_t(0)) / p.L));
-    hi = min(hi, int32_t(min(int64_t(g.xhi) + hw, int64_t(DPC_COORD_LIMIT - 1)) / p.L));
+    // clamped into [0, 2^17) first, so the divisions are 32-bit
+    const int32_t a = int32_t(max(int64_t(g.xlo) - hw, int64_t(0)));
+    const int32_t c = int32_t(min(int64_t(g.xhi) + hw, int64_t(DPC_COORD_LIMIT - 1)));
+    lo = max(lo, a / p.L);
+    hi = min(hi, c / p.L);
     if (lo > hi) return;
   }
   *b = start[rowk * p.nc + lo];
