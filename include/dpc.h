@@ -154,7 +154,8 @@ typedef struct {
   int32_t subdiv;          /* cells per cut-off distance along each axis (1..16) */
   int32_t strip_cells;     /* narrower task strips (cells along the last axis) */
   int32_t nstages;         /* dependent-search window stages (1..4), radii and groups below */
-  int32_t stage_radius[4]; /* window radius of each stage in cells (1..64) */
+  int32_t stage_radius[4]; /* window radius of each stage in cells (1..64); 0: the density
+                              window clipped to the cut-off ball (final when closer than d_cut) */
   int32_t stage_group[4];  /* tasks whose open points one wave gathers (1..64) */
   int32_t ring_cap;        /* most ring-search steps per point before the prefix scan */
   int32_t grid_dims;       /* coordinates the cells index (default d up to 4, else 3; d if

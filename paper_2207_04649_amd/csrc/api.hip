@@ -153,7 +153,7 @@ dpc_tuning env_tuning() {
 bool valid_stages(const dpc_tuning &t) {
   if (t.nstages < 1 || t.nstages > 4) return false;
   for (int k = 0; k < t.nstages; ++k)
-    if (t.stage_radius[k] < 1 || t.stage_radius[k] > 64 || t.stage_group[k] < 1 || t.stage_group[k] > 64)
+    if (t.stage_radius[k] < 0 || t.stage_radius[k] > 64 || t.stage_group[k] < 1 || t.stage_group[k] > 64)
       return false;
   return true;
 }
@@ -252,11 +252,11 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   }
   p.nstages = 0;
   for (int k = 0; k < st.nstages; ++k) {
-    const int K = st.stage_radius[k];
+    const int K = st.stage_radius[k] == 0 ? p.K0 : st.stage_radius[k];  // 0: the ball stage
     int64_t rows = 1;
     for (int t = 0; t < gm - 1; ++t) rows *= 2 * K + 1;
     if (k > 0 && rows > 4096) break;
-    p.stageK[p.nstages] = K;
+    p.stageK[p.nstages] = st.stage_radius[k];
     p.stageGroup[p.nstages] = st.stage_group[k];
     p.stageMode[p.nstages] = (gm == d && p16_ok(K, p.wc)) ? kModeP16 : kModeI64;
     ++p.nstages;

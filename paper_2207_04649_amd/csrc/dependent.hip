@@ -30,9 +30,16 @@ namespace {
 
 // One window search for up to 64 open points of one strip (lane = point; lanes
 // with valid = false repeat a valid lane's point and store the same values).
+//
+// K >= 1: the window of radius K cells; a point is final when its best is
+// strictly closer than the window's exterior.  K == 0 (ball stage): the density
+// window (radius K0, clipped to the d_cut-balls), which holds every point closer
+// than d_cut to each query; a point is final when its best is inside its ball.
 template <int D, int MODE>
-__device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int K, bool first, uint32_t strip,
+__device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int Kin, bool first, uint32_t strip,
                                              uint32_t q, bool valid) {
+  const bool ball = Kin == 0;
+  const int K = ball ? p.K0 : Kin;
   constexpr int W = (D + 1) / 2;
   const int lane = lane_id();
   DPC_CONST(uint32_t) *spk = as_const(w.spk);
@@ -50,8 +57,11 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int K, 
   uint64_t best = first ? kNoKey : w.best[id];
   // Clip the window to the largest best distance when every point has one.
   const bool all_have = __ballot(valid && best == kNoKey) == 0;
-  uint64_t clip2 = ~uint64_t(0);
-  if (all_have) clip2 = uniform(wave_max_u64(valid ? (best >> kIdBits) : uint64_t(0)));
+  uint64_t clip2 = ball ? uint64_t(p.R - 1) : ~uint64_t(0);
+  if (all_have) {
+    const uint64_t c = uniform(wave_max_u64(valid ? (best >> kIdBits) : uint64_t(0)));
+    clip2 = c < clip2 ? c : clip2;
+  }
   uint32_t qk[W];
   if (MODE == kModeP16) {
 #pragma unroll
@@ -118,7 +128,8 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int K, 
   }
   if (MODE == kModeP16 && best != kNoKey) best = ((best >> 32) << kIdBits) | (best & 0xFFFFFFFFu);
   const uint64_t ext = window_exterior_d2<D>(p, g, K, qx);
-  const bool resolved = ext == kNoKey || (best != kNoKey && (best >> kIdBits) < ext);
+  const uint64_t bound = ball ? uint64_t(p.R) : ext;  // every point closer than this was searched
+  const bool resolved = ext == kNoKey || (best != kNoKey && (best >> kIdBits) < bound);
   w.best[id] = best;
   w.flag[q] = resolved ? 0 : 1;
 }
@@ -289,7 +300,7 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
     int32_t k0 = k_start;
 
     for (;;) {
-      const int32_t k1 = 2 * k0;
+      const int32_t k1 = k0 < 1 ? 1 : 2 * k0;  // k0 = -1: nothing searched yet
       const int64_t side = 2 * int64_t(k1) + 1;
       int64_t nrows = 1;
       for (int t = 0; t < p.gm - 1; ++t) nrows *= side;
@@ -572,7 +583,8 @@ __global__ __launch_bounds__(kBlock) void kb_collect(const JobDev *jobs, VMap m)
 template <int D>
 __global__ __launch_bounds__(kBlock) void kb_ringk(const JobDev *jobs, VMap m) {
   DPC_FOR_VBLOCKS(m)
-  ringk_body<D>(k, p, w, uniform(int32_t(as_const(jobs)[j].p.stageK[p.nstages - 1])));
+  const int kl = uniform(int32_t(as_const(jobs)[j].p.stageK[p.nstages - 1]));
+  ringk_body<D>(k, p, w, kl == 0 ? -1 : kl);  // after a ball stage no cell block is known searched
 }
 }
 
@@ -608,7 +620,8 @@ hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta,
   {
     ProfScope ps(s, kProfRingK);
     DPC_LAUNCH((k_collect), blocks_for(p.n, kBlock * kCollectPer), kBlock, s, p, w);
-    DPC_LAUNCH((k_ringk<D>), rb, kBlock, s, p, w, p.stageK[p.nstages - 1]);
+    const int kl = p.stageK[p.nstages - 1];
+    DPC_LAUNCH((k_ringk<D>), rb, kBlock, s, p, w, kl == 0 ? -1 : kl);  // after a ball stage: nothing
   }
   {
     ProfScope ps(s, kProfPeaks);

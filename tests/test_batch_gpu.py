@@ -128,7 +128,9 @@ def test_batch_rerun_and_tunings_agree(dpc):
         pins.assert_same(to_host(o), first[k], keys=KEYS, ctx=f"rerun job {k}")
     b.close()
     tun = [dpc.Tuning.make(subdiv=1 + k % 4, strip_cells=(0, 3, 16)[k % 3],
-                           stages=[((1, 1), (3, 4)), ((2, 1),), ((1, 1), (2, 2), (4, 8))][k % 3], ring_cap=(0, 4, 300)[k % 3])
+                           stages=[((1, 1), (3, 4)), ((2, 1),), ((1, 1), (2, 2), (4, 8)), ((0, 1),),
+                                   ((0, 1), (2, 4))][k % 5],
+                           ring_cap=(0, 4, 300)[k % 3], grid_dims=(0, 2, 3, 8)[k % 4], row_split=(0, 2, 9)[k % 3])
            for k in range(len(jobs))]
     b2, _, tuned = run_batch(dpc, jobs, tun)
     for k in range(len(jobs)):

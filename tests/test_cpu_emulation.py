@@ -40,19 +40,19 @@ def _parse(b, o, n):
     return out, o
 
 
-def _run(exe, args, payload):
+def _run(exe, args, payload, extra_env=None):
     with tempfile.TemporaryDirectory() as tmp:
         fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
         with open(fin, "wb") as f:
             f.write(payload)
-        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:detect_stack_use_after_return=0")
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:detect_stack_use_after_return=0", **(extra_env or {}))
         r = subprocess.run([exe, *args, fin, fout], capture_output=True, text=True, timeout=600, env=env)
         assert r.returncode == 0, r.stderr[-3000:]
         return open(fout, "rb").read()
 
 
-def run_emu(exe, pts, d_cut, rho_min, delta_min):
-    b = _run(exe, [], _record(pts, d_cut, rho_min, delta_min))
+def run_emu(exe, pts, d_cut, rho_min, delta_min, extra_env=None):
+    b = _run(exe, [], _record(pts, d_cut, rho_min, delta_min), extra_env)
     return _parse(b, 0, int(np.asarray(pts).shape[0]))[0]
 
 
@@ -118,3 +118,19 @@ def test_emulated_batch_matches_oracle(emu_exe):
     for k, (job, got) in enumerate(zip(jobs, outs)):
         assert got["status"] == 0 and got["sync"] == 0, k
         pins.assert_same(got, pins.run(scan, *job), keys=("rho", "dep", "delta", "label", "ncenters"), ctx=f"job {k}")
+
+
+@pytest.mark.parametrize("env", [
+    {"DPC_STAGES": "0:1"},                                  # ball stage, ring search from nothing
+    {"DPC_STAGES": "0:1,2:4", "DPC_GRID_DIMS": "2"},       # ball then a gathered stage, partial grid
+    {"DPC_STAGES": "1:1,3:4", "DPC_ROW_SPLIT": "3", "DPC_SUBDIV": "3"},
+])
+def test_emulated_plan_options_match_oracle(emu_exe, env):
+    for k, (n, d, dc) in enumerate([(300, 2, 4000.0), (200, 4, 12000.0)]):
+        pts = inputs.uniform_points(n, d, 131071, 500 + k)
+        pts[n // 2:] = pts[: n - n // 2] + (pts[: n - n // 2] % 5)
+        pts = np.clip(pts, 0, 131071).astype(np.int32)
+        got = run_emu(emu_exe, pts, dc, 2, dc * 1.5, extra_env=env)
+        assert got["status"] == 0 and got["sync"] == 0
+        pins.assert_same(got, pins.run(scan, pts, dc, 2, dc * 1.5), keys=("rho", "dep", "delta", "label", "ncenters"),
+                         ctx=f"{env} n={n} d={d}")
