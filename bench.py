@@ -40,14 +40,14 @@ def density_ops(d: int) -> int:
 
 # HBM bytes of the density kernel per launch, from two rocprofv3 --pmc runs of
 # this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the
-# kernel's dispatches).  A plain 256 MiB device copy read back 131088.4 KiB of
+# kernel's dispatches).  A plain 256 MiB device copy read back 131088.3 KiB of
 # FETCH_SIZE and a 256 MiB fill wrote 262144 KiB of WRITE_SIZE, so fetches are
-# scaled by 262144 / 131088.4 and writes by 1.  The figures belong to the kernel
+# scaled by 262144 / 131088.3 and writes by 1.  The figures belong to the kernel
 # sources they were taken with: if those change, traffic is reported as null.
 DENSITY_SOURCES = ("paper_2207_04649_amd/csrc/density.hip", "paper_2207_04649_amd/csrc/tasks.h",
                    "paper_2207_04649_amd/csrc/common.h")
-DENSITY_HBM = {"blobs_1m_d2": {"source": "71cdbab751e8182e", "fetch_kib": 50779.2, "write_kib": 44902.5}}
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.4375, 1.0
+DENSITY_HBM = {"blobs_1m_d2": {"source": "dcf06f00b6e0f1d9", "fetch_kib": 32093.1, "write_kib": 37763.4}}
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.3125, 1.0
 
 
 def source_hash(files) -> str:
