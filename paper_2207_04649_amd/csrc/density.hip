@@ -161,11 +161,15 @@ hipError_t launch_d(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s, uns
 }  // namespace
 
 unsigned persistent_blocks(int64_t max_items) {
-  // 256 CUs x 8 resident workgroups of 4 waves; fewer when there is less work.
+  // One wave per item up to kGridCap blocks, 16 times the 2048 workgroups of 4
+  // waves that the 256 CUs hold at once (fewer when there is less work).  Work
+  // per item varies several-fold (a task's window holds tens to thousands of
+  // candidates), and a grid larger than the resident set lets the hardware
+  // dispatcher start a new workgroup wherever one has finished: a dynamic
+  // balance with no shared counter.
   int64_t waves = max_items < 1 ? 1 : max_items;
   int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-  const int64_t cap = 256 * 8;
-  return static_cast<unsigned>(blocks < cap ? blocks : cap);
+  return static_cast<unsigned>(blocks < kGridCap ? blocks : kGridCap);
 }
 
 hipError_t launch_density(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s) {

@@ -139,6 +139,7 @@ def test_plan_options_are_checked_and_applied():
     p = dpc.dpc_plan_tuned(1_000_000, 2, 200.0, t)
     assert p["cell_side"] == 100 and p["strip_cells"] == 5 and p["stages"] == 3
     with pytest.raises(dpc.DpcError):
-        dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(0, 1)]))
+        dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(65, 1)]))
+    assert dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(0, 1)]))["stages"] == 1  # ball stage
     with pytest.raises(dpc.DpcError):
         dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(1, 99)]))
