@@ -124,14 +124,22 @@ __device__ __forceinline__ void cell_keys(Blk k, const int32_t *__restrict__ pts
   }
 }
 
-// Place every point at start[key] + slot: clamped coordinates, their packed low
-// 16 bits, and the id.
-__device__ __forceinline__ void scatter(Blk k, const int32_t *__restrict__ pts, const Plan &p,
-                                        const uint32_t *__restrict__ start, const uint32_t *__restrict__ key,
-                                        const uint32_t *__restrict__ slot, int32_t *__restrict__ spts,
-                                        uint32_t *__restrict__ spk, int32_t *__restrict__ sid) {
-  for (int64_t i = thread_index(k); i < p.n; i += grid_threads(k)) {
-    const int64_t pos = int64_t(start[key[i]]) + slot[i];
+// Place every point's id at start[key] + slot: one scattered 4-byte store per
+// point.  The coordinates follow in cell order in gather_pts, so that their
+// stores are contiguous and only the reads of the (cache-resident) input scatter.
+__device__ __forceinline__ void scatter_ids(Blk k, const Plan &p, const uint32_t *__restrict__ start,
+                                            const uint32_t *__restrict__ key, const uint32_t *__restrict__ slot,
+                                            int32_t *__restrict__ sid) {
+  for (int64_t i = thread_index(k); i < p.n; i += grid_threads(k)) sid[int64_t(start[key[i]]) + slot[i]] = int32_t(i);
+}
+
+// Cell-ordered copies of the point at each position: clamped coordinates and
+// their packed low 16 bits.
+__device__ __forceinline__ void gather_pts(Blk k, const int32_t *__restrict__ pts, const Plan &p,
+                                           const int32_t *__restrict__ sid, int32_t *__restrict__ spts,
+                                           uint32_t *__restrict__ spk) {
+  for (int64_t pos = thread_index(k); pos < p.n; pos += grid_threads(k)) {
+    const int64_t i = sid[pos];
     uint32_t w = 0;
     for (int t = 0; t < p.d; ++t) {
       int32_t x = pts[i * p.d + t];
@@ -144,7 +152,6 @@ __device__ __forceinline__ void scatter(Blk k, const int32_t *__restrict__ pts, 
       }
     }
     if (p.d & 1) spk[pos * p.words + (p.d >> 1)] = w;
-    sid[pos] = int32_t(i);
   }
 }
 
@@ -291,8 +298,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *data, int64_t cou
 __global__ __launch_bounds__(kBlock) void k_cell_keys(const int32_t *pts, Plan p, Ws w) {
   cell_keys(grid_blk(), pts, p, w.cnt, w.key, w.slot, w.hdr);
 }
-__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t *pts, Plan p, Ws w) {
-  scatter(grid_blk(), pts, p, w.cnt, w.key, w.slot, w.spts, w.spk, w.sid);
+__global__ __launch_bounds__(kBlock) void k_scatter(Plan p, Ws w) {
+  scatter_ids(grid_blk(), p, w.cnt, w.key, w.slot, w.sid);
+}
+__global__ __launch_bounds__(kBlock) void k_gather_pts(const int32_t *pts, Plan p, Ws w) {
+  gather_pts(grid_blk(), pts, p, w.sid, w.spts, w.spk);
 }
 __global__ __launch_bounds__(kBlock) void k_strip_count(Plan p, Ws w) { strip_count(grid_blk(), p, w.cnt, w.tcnt); }
 __global__ __launch_bounds__(kBlock) void k_strip_tasks(Plan p, Ws w) {
@@ -394,7 +404,13 @@ __global__ __launch_bounds__(kBlock) void kb_cell_keys(const JobDev *jobs, VMap 
 
 __global__ __launch_bounds__(kBlock) void kb_scatter(const JobDev *jobs, VMap m) {
   DPC_FOR_VBLOCKS(m)
-  scatter(k, as_const(jobs)[j].pts, p, w.cnt, w.key, w.slot, w.spts, w.spk, w.sid);
+  scatter_ids(k, p, w.cnt, w.key, w.slot, w.sid);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_gather_pts(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  gather_pts(k, as_const(jobs)[j].pts, p, w.sid, w.spts, w.spk);
 }
 }
 
@@ -474,7 +490,8 @@ hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, hipStream_
   if ((e = launch_fill_u32(w.cnt, 0u, p.ncells + 1, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_cell_keys), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
   if ((e = launch_scan(w.cnt, p.ncells + 1, w.bsum, s)) != hipSuccess) return e;
-  DPC_LAUNCH((k_scatter), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
+  DPC_LAUNCH((k_scatter), blocks_for(p.n, kBlock), kBlock, s, p, w);
+  DPC_LAUNCH((k_gather_pts), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
   DPC_LAUNCH((k_strip_count), blocks_for(p.nstrips + 1, kBlock), kBlock, s, p, w);
   if ((e = launch_scan(w.tcnt, p.nstrips + 1, w.bsum, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_strip_tasks), blocks_for(p.nstrips, kBlock), kBlock, s, p, w);
@@ -507,6 +524,7 @@ hipError_t batch_build_grid(const BatchMaps &B, hipStream_t s) {
   if (vgrid(B.pts)) DPC_LAUNCH((kb_cell_keys), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   batch_scan<kArrCells>(B, B.cells, s);
   if (vgrid(B.pts)) DPC_LAUNCH((kb_scatter), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  if (vgrid(B.pts)) DPC_LAUNCH((kb_gather_pts), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   if (vgrid(B.strips)) DPC_LAUNCH((kb_strip_count), vgrid(B.strips), kBlock, s, B.jobs, B.strips);
   batch_scan<kArrStrips>(B, B.strips, s);
   if (vgrid(B.strips)) DPC_LAUNCH((kb_strip_tasks), vgrid(B.strips), kBlock, s, B.jobs, B.strips);
