@@ -46,7 +46,7 @@ def density_ops(d: int) -> int:
 # sources they were taken with: if those change, traffic is reported as null.
 DENSITY_SOURCES = ("paper_2207_04649_amd/csrc/density.hip", "paper_2207_04649_amd/csrc/tasks.h",
                    "paper_2207_04649_amd/csrc/common.h")
-DENSITY_HBM = {"blobs_1m_d2": {"source": "4a08fbe3514f8f51", "fetch_kib": 30418.5, "write_kib": 37489.9}}
+DENSITY_HBM = {"blobs_1m_d2": {"source": "4a08fbe3514f8f51", "fetch_kib": 30365.0, "write_kib": 37473.2}}
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.3125, 1.0
 
 

@@ -169,17 +169,33 @@ __device__ __forceinline__ void scatter_ids(Blk k, const Plan &p, const uint32_t
   for (int64_t i = thread_index(k); i < p.n; i += grid_threads(k)) sid[int64_t(start[key[i]]) + slot[i]] = int32_t(i);
 }
 
+__device__ __forceinline__ int32_t clamp_coord(int32_t x) {
+  return x < 0 ? 0 : (x >= DPC_COORD_LIMIT ? DPC_COORD_LIMIT - 1 : x);
+}
+
 // Cell-ordered copies of the point at each position: clamped coordinates and
 // their packed low 16 bits.
 __device__ __forceinline__ void gather_pts(Blk k, const int32_t *__restrict__ pts, const Plan &p,
                                            const int32_t *__restrict__ sid, int32_t *__restrict__ spts,
                                            uint32_t *__restrict__ spk) {
+  // Four-coordinate rows of 16-byte aligned arrays move as one 16-byte vector.
+  const bool v4 = p.d == 4 && ((reinterpret_cast<uintptr_t>(pts) | reinterpret_cast<uintptr_t>(spts)) & 15u) == 0;
   for (int64_t pos = thread_index(k); pos < p.n; pos += grid_threads(k)) {
     const int64_t i = sid[pos];
+    if (v4) {
+      uint4 a = reinterpret_cast<const uint4 *>(pts)[i];
+      a.x = uint32_t(clamp_coord(int32_t(a.x)));
+      a.y = uint32_t(clamp_coord(int32_t(a.y)));
+      a.z = uint32_t(clamp_coord(int32_t(a.z)));
+      a.w = uint32_t(clamp_coord(int32_t(a.w)));
+      reinterpret_cast<uint4 *>(spts)[pos] = a;
+      spk[pos * p.words] = (a.x & 0xFFFFu) | (a.y << 16);
+      spk[pos * p.words + 1] = (a.z & 0xFFFFu) | (a.w << 16);
+      continue;
+    }
     uint32_t w = 0;
     for (int t = 0; t < p.d; ++t) {
-      int32_t x = pts[i * p.d + t];
-      x = x < 0 ? 0 : (x >= DPC_COORD_LIMIT ? DPC_COORD_LIMIT - 1 : x);
+      const int32_t x = clamp_coord(pts[i * p.d + t]);
       spts[pos * p.d + t] = x;
       w |= (uint32_t(x) & 0xFFFFu) << (16 * (t & 1));
       if (t & 1) {
