@@ -84,20 +84,26 @@ void oracle_order(const int32_t *rho, int64_t n, int64_t *order) {
     qsort(order, (size_t)n, sizeof(int64_t), by_density);
 }
 
-/* Step 3 / Defs. 2-3: scan the sorted array up to the point itself. */
+/* Step 3 / Defs. 2-3: scan the sorted array up to the point itself.  As in
+ * step 2, the points themselves are put in density order (sorted[k] is the
+ * point order[k]), so the scan of every prefix reads memory in sequence. */
 void oracle_dependent(const int32_t *pts, int64_t n, int32_t d, const int32_t *rho,
                       int32_t *dep, int64_t *d2) {
     int64_t *order = (int64_t *)malloc((size_t)n * sizeof(int64_t));
     int64_t *rank = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int32_t *sorted = (int32_t *)malloc((size_t)n * (size_t)d * sizeof(int32_t));
     oracle_order(rho, n, order);
-    for (int64_t r = 0; r < n; r++) rank[order[r]] = r;
+    for (int64_t r = 0; r < n; r++) {
+        rank[order[r]] = r;
+        memcpy(sorted + r * d, pts + order[r] * d, (size_t)d * sizeof(int32_t));
+    }
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; i++) {
         const int32_t *a = pts + i * d;
         int64_t best = INT64_MAX, bj = -1;
         for (int64_t k = 0; k < rank[i]; k++) {
             int64_t j = order[k];
-            int64_t s = sqdist(a, pts + j * d, d);
+            int64_t s = sqdist(a, sorted + k * d, d);
             if (s < best || (s == best && j < bj)) {
                 best = s;
                 bj = j;
@@ -108,6 +114,7 @@ void oracle_dependent(const int32_t *pts, int64_t n, int32_t d, const int32_t *r
     }
     free(order);
     free(rank);
+    free(sorted);
 }
 
 typedef struct {
