@@ -3,13 +3,16 @@
 
 One step = dpc_run on the resident input: grid build, local density (Def. 1),
 density-rank sort, dependent point and distance (Defs. 2-3) and labels (Defs.
-4-6), i.e. every step of the hot path, on the 1,000,000-point 2-D blob workload
-(50 Gaussian blobs, sigma log-uniform in [300, 3000], 10% uniform noise, int32
-coordinates in [0, 100000], d_cut = 200, rho_min = 20, delta_min = 3000).
+4-6), i.e. every step of the hot path.  The default workload is the
+4,000,000-point 4-D random-walk set (100 reflecting walks with N(0, 500^2)
+steps plus 2% uniform noise, int32 coordinates in [0, 100000], d_cut = 1500,
+rho_min = 30, delta_min = 8000); ``--extra`` adds a shorter run of a second
+workload (default the 1,000,000-point 2-D blob set) as an extra key.
 
-Prints one JSON line: points/s, the roofline of the dominant kernel (timed with
-HIP events on the library's stream inside the timed region) and the oracle's
-CPU throughput on a bounded sample.
+Prints one JSON line: points/s, the roofline of the dominant kernel group and
+of every group (timed with HIP events on the library's stream inside the timed
+region), the kernels' candidate-test counts, and the oracle's CPU throughput on
+a bounded sample.
 """
 from __future__ import annotations
 
@@ -29,25 +32,70 @@ HBM_PEAK_GBS = 8000.0
 CUS, SIMDS_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
 VALU_PEAK_TOPS = CUS * SIMDS_PER_CU * LANES_PER_SIMD * CLOCK_GHZ / 1000.0  # 32-bit lane-ops/s, in T
 
-# Algorithmic work of the local density (Def. 1): the sum of rho over all
-# points is the number of in-ball distance tests no exact method can skip; a
-# plain test costs 2d + 2 32-bit lane ops (a subtract and a multiply-add per
-# dimension, a compare and a count).  The kernel's rate of useful tests, in
-# those ops, against the chip's 32-bit VALU peak gives its roofline fraction.
-def density_ops(d: int) -> int:
+
+# A distance test of two d-dimensional points costs 2d + 2 32-bit lane ops in a
+# plain form (a subtract and a multiply-add per dimension, a compare and a
+# count or select).  Rates of tests in those ops, against the chip's 32-bit
+# VALU peak, give the ALU rooflines.
+def test_ops(d: int) -> int:
     return 2 * d + 2
 
 
-# HBM bytes of the density kernel per launch, from two rocprofv3 --pmc runs of
-# this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the
-# kernel's dispatches).  A plain 256 MiB device copy read back 131088.3 KiB of
-# FETCH_SIZE and a 256 MiB fill wrote 262144 KiB of WRITE_SIZE, so fetches are
-# scaled by 262144 / 131088.3 and writes by 1.  The figures belong to the kernel
-# sources they were taken with: if those change, traffic is reported as null.
-DENSITY_SOURCES = ("paper_2207_04649_amd/csrc/density.hip", "paper_2207_04649_amd/csrc/tasks.h",
-                   "paper_2207_04649_amd/csrc/common.h")
-DENSITY_HBM = {"blobs_1m_d2": {"source": "4a08fbe3514f8f51", "fetch_kib": 30365.0, "write_kib": 37473.2}}
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131088.3125, 1.0
+def grid_bytes(n: int, d: int, cells: int) -> int:
+    """Algorithmic HBM bytes of the grid build (a counting sort into cells): read the
+    coordinates (4d per point) for the keys, write key and slot (8), read them and write
+    the id and position (16), read the id and the coordinates and write the cell-order
+    coordinates and their packed copy (4 + 8d + 4 ceil(d/2)); the cell table is zeroed,
+    read and written by the scan (12 per cell)."""
+    w = (d + 1) // 2
+    return n * (4 * d + 8 + 16 + 4 + 8 * d + 4 * w) + 12 * (cells + 1)
+
+
+def rooflines(job, per_ms: dict, sum_rho: int, work: dict, plan: dict) -> dict:
+    """Roofline of each kernel group:
+
+    * density (ALU): the algorithmic work is sum(rho), the in-ball tests no exact
+      method can skip (Def. 1), each at test_ops(d);
+    * search, ringk, peaks (ALU): the candidate tests each makes (counted by the
+      kernels in an instrumented call), at test_ops(d): the pairs of a point and a
+      point of higher rank in its searched cells (Defs. 2-3);
+    * grid_build (HBM): grid_bytes() against 8 TB/s.
+    """
+    ops = test_ops(job.d)
+    out = {}
+
+    def alu(name, tests, algorithmic):
+        t = per_ms.get(name)
+        if not t:
+            return
+        a = tests * ops / (t * 1e-3) / 1e12
+        out[name] = {"avg_ms": t, "bound": "alu", "achieved": a, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                     "frac": a / VALU_PEAK_TOPS, "traffic": kernel_traffic(name, job.name),
+                     "tests_per_launch": tests, "ops_per_test": ops, "work": algorithmic}
+
+    alu("density", sum_rho, "sum of rho (in-ball pairs, self included)")
+    alu("search", work.get("tests_search", 0), "candidate tests of the window search")
+    alu("ringk", work.get("tests_ring", 0), "candidate tests of the ring search")
+    alu("peaks", work.get("tests_peaks", 0), "candidate tests of the prefix scan")
+    t = per_ms.get("grid_build")
+    if t:
+        b = grid_bytes(job.n, job.d, plan["cells"])
+        a = b / (t * 1e-3) / 1e9
+        out["grid_build"] = {"avg_ms": t, "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": a / HBM_PEAK_GBS, "traffic": kernel_traffic("grid_build", job.name),
+                             "bytes_per_launch": b}
+    return out
+
+
+# HBM bytes per launch of the kernel groups, from two rocprofv3 --pmc runs of this
+# script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# counter reads for a plain copy of known size in the same run (see
+# paper_2207_04649_amd/prof_summary.py hbm).  The figures belong to the kernel
+# sources they were taken with: when those change, traffic is reported as null.
+KERNEL_SOURCES = ("paper_2207_04649_amd/csrc/density.hip", "paper_2207_04649_amd/csrc/dependent.hip",
+                  "paper_2207_04649_amd/csrc/grid.hip", "paper_2207_04649_amd/csrc/tasks.h",
+                  "paper_2207_04649_amd/csrc/common.h")
+HBM_BYTES: dict = {}  # {workload: {"source": hash, group: bytes per launch}}
 
 
 def source_hash(files) -> str:
@@ -60,11 +108,11 @@ def source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
-def density_traffic(workload: str):
-    rec = DENSITY_HBM.get(workload)
-    if rec is None or rec["source"] != source_hash(DENSITY_SOURCES):
+def kernel_traffic(group: str, workload: str):
+    rec = HBM_BYTES.get(workload)
+    if rec is None or rec.get("source") != source_hash(KERNEL_SOURCES):
         return None
-    return (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE) * 1024.0
+    return rec.get(group)
 
 
 def cpu_baseline(job, budget_s: float) -> dict:
@@ -251,7 +299,7 @@ def bench_batch(args, jobs) -> int:
     same = all(torch.equal(b.out[k][f], outs[k][f]) for k in range(0, len(jobs), max(1, len(jobs) // 256))
                for f in ("rho", "dep", "delta", "label", "ncenters"))
 
-    sum_ops = sum(int(o["rho"].sum().item()) * density_ops(j.d) for o, j in zip(b.out, jobs))
+    sum_ops = sum(int(o["rho"].sum().item()) * test_ops(j.d) for o, j in zip(b.out, jobs))
     dens_ms = prof["density"][1] / max(1, prof["density"][0])
     achieved = sum_ops / (dens_ms * 1e-3) / 1e12
     line = {
@@ -273,7 +321,7 @@ def bench_batch(args, jobs) -> int:
         "per_job_launches": {"value": total / single_s, "ms_per_step": single_s * 1e3},
         "batched_vs_per_job": single_s / batched_s,
         "batch_equals_per_job": same,
-        "autotune": {str(d): v["options"] for d, v in table.items()},
+        "autotune": {f"d{k[0]}_size{k[1]}": v["options"] for k, v in table.items()},
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in prof.items() if k != "work" and v[0]},
         "roofline": {"kernel": "density", "avg_ms": dens_ms, "bound": "alu", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None},
@@ -288,7 +336,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="blobs_1m_d2")
+    ap.add_argument("--workload", default="walks_4m_d4")
+    ap.add_argument("--extra", default="blobs_1m_d2", help="a second workload measured as an extra key ('' for none)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jobs", type=int, default=4096, help="jobs of the batch4096 workload")
@@ -326,53 +375,15 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     job = inputs.WORKLOADS[args.workload]()
-    dev = torch.device("cuda:0")
-    pts = torch.from_numpy(job.pts).to(dev)
-    ws = dpc.workspace(job.n, job.d, job.d_cut, dev)
-    out: dict = {}
-    for _ in range(args.warmup):
-        dpc.dpc_run(pts, job.d_cut, job.rho_min, job.delta_min, ws=ws, out=out)
-    torch.cuda.synchronize()
-    dpc.dpc_sync_status(ws)
-
-    L = dpc.lib()
-    L.dpc_profile_enable.argtypes = [ctypes.c_int32]
-    L.dpc_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
-    L.dpc_profile_report.restype = ctypes.c_int32
-    buf = ctypes.create_string_buffer(4096)
-    L.dpc_profile_report(buf, 4096)  # clear
-    L.dpc_profile_enable(1)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        dpc.dpc_run(pts, job.d_cut, job.rho_min, job.delta_min, ws=ws, out=out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    L.dpc_profile_enable(0)
-    L.dpc_profile_report(buf, 4096)
-    prof = json.loads(buf.value.decode())
-    dpc.dpc_sync_status(ws)
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-
-    # Roofline of the density kernel (HIP events on the library's stream).
-    per = {k: v[1] / max(1, v[0]) for k, v in prof.items() if k != "work" and v[0]}
-    dom = max(per, key=per.get)
-    sum_rho = int(out["rho"].sum().item())
-    evals = sum_rho
-    achieved = evals * density_ops(job.d) / (per["density"] * 1e-3) / 1e12
-    roof = {"kernel": "density", "avg_ms": per["density"], "bound": "alu", "achieved": achieved,
-            "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": density_traffic(job.name),
-            "evals_per_launch": evals, "ops_per_eval": density_ops(job.d), "slowest_group": dom}
-
+    res = bench_single(args, job, args.steps, args.warmup, with_roofline=True)
     line = {
         "metric": "points/s end-to-end DPC (rho+delta+labels) at 1 MI355X",
-        "value": job.n * args.steps / (t1 - t0),
+        "value": res["value"],
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -380,14 +391,87 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": job.name, "n": job.n, "d": job.d, "d_cut": job.d_cut, "rho_min": job.rho_min,
                    "delta_min": job.delta_min},
-        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in prof.items() if k != "work" and v[0]},
-        "roofline": roof,
-        "ncenters": int(out["ncenters"].item()),
+        "kernels_ms_per_step": res["kernels_ms_per_step"],
+        "roofline": res["roofline"],
+        "rooflines": res["rooflines"],
+        "work": res["work"],
+        "ncenters": res["ncenters"],
     }
+    if args.extra and args.extra != job.name:
+        ex = inputs.WORKLOADS[args.extra]()
+        r2 = bench_single(args, ex, max(3, args.steps // 2), 2, with_roofline=True)
+        line["extra"] = {ex.name: {"value": r2["value"], "unit": "points/s", "ms_per_step": r2["ms_per_step"],
+                                   "kernels_ms_per_step": r2["kernels_ms_per_step"],
+                                   "roofline": r2["roofline"]}}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(job, args.cpu_budget)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def _profile_lib():
+    from paper_2207_04649_amd import dpc
+
+    L = dpc.lib()
+    L.dpc_profile_enable.argtypes = [ctypes.c_int32]
+    L.dpc_profile_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    L.dpc_profile_report.restype = ctypes.c_int32
+    return L
+
+
+def _report(L) -> dict:
+    buf = ctypes.create_string_buffer(8192)
+    L.dpc_profile_report(buf, 8192)
+    return json.loads(buf.value.decode())
+
+
+def bench_single(args, job, steps: int, warmup: int, with_roofline: bool) -> dict:
+    """Time `steps` dpc_run calls on resident input (HIP events per kernel group on the
+    library's stream inside the timed region), then one untimed instrumented call for
+    the kernels' candidate-test counts."""
+    import torch
+
+    from paper_2207_04649_amd import dpc
+
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(job.pts).to(dev)
+    ws = dpc.workspace(job.n, job.d, job.d_cut, dev)
+    out: dict = {}
+    for _ in range(warmup):
+        dpc.dpc_run(pts, job.d_cut, job.rho_min, job.delta_min, ws=ws, out=out)
+    torch.cuda.synchronize()
+    dpc.dpc_sync_status(ws)
+
+    L = _profile_lib()
+    _report(L)  # clear
+    L.dpc_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dpc.dpc_run(pts, job.d_cut, job.rho_min, job.delta_min, ws=ws, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.dpc_profile_enable(0)
+    prof = _report(L)
+    dpc.dpc_sync_status(ws)
+
+    # one more call, untimed, counting each kernel's candidate tests
+    L.dpc_profile_enable(2)
+    dpc.dpc_run(pts, job.d_cut, job.rho_min, job.delta_min, ws=ws, out=out)
+    torch.cuda.synchronize()
+    L.dpc_profile_enable(0)
+    work = _report(L)["work"]
+    dpc.dpc_sync_status(ws)
+
+    per = {k: v[1] / max(1, v[0]) for k, v in prof.items() if k != "work" and v[0]}
+    sum_rho = int(out["rho"].sum().item())
+    plan = dpc.dpc_plan(job.n, job.d, job.d_cut)
+    roofs = rooflines(job, per, sum_rho, work, plan)
+    dom = max((k for k in per if k in roofs), key=per.get)
+    return {"value": job.n * steps / (t1 - t0), "ms_per_step": (t1 - t0) * 1000.0 / steps,
+            "kernels_ms_per_step": {k: v[1] / steps for k, v in prof.items() if k != "work" and v[0]},
+            "roofline": dict(roofs[dom], kernel=dom), "rooflines": roofs,
+            "work": dict(work, sum_rho=sum_rho), "ncenters": int(out["ncenters"].item())}
 
 
 if __name__ == "__main__":

@@ -56,7 +56,11 @@ typedef int32_t dpc_status;
 #define DPC_EDEVICE (-4)    /* HIP runtime error; dpc_last_error() gives the message */
 
 /* Flag for dpc_dependent: `ws` still holds the grid that dpc_density built for the same
- * pts, n, d and d_cut, so it is not rebuilt. */
+ * pts, n, d and d_cut, so it is not rebuilt.  The grid carries a stamp of the inputs it
+ * was built for, checked on the device: if it does not match (no dpc_density call on this
+ * workspace, or one with other inputs), nothing is computed, the outputs are left as they
+ * were and dpc_sync_status reports DPC_EINVAL.  A reused grid keeps its build's status
+ * (DPC_ERANGE when a coordinate was clamped). */
 #define DPC_REUSE_GRID 1u
 
 /* Largest number of points per call (ids must fit 27 bits of a packed (D2, id) key). */
@@ -126,6 +130,7 @@ typedef struct {
   int64_t window_radius; /* K0 cells: K0 * L >= floor(sqrt(R - 1)), so (2 K0 + 1)^d cells hold a d_cut-ball */
   int64_t stages;        /* dependent-search stages */
   int64_t grid_dims;     /* coordinates the cells index (the first grid_dims of d) */
+  int64_t lanes;         /* kernel form: 0 tasks of 64 queries sharing windows, 1 one query per lane */
 } dpc_plan_info;
 dpc_status dpc_plan(int64_t n, int32_t d, double d_cut, dpc_plan_info *out);
 
@@ -146,21 +151,25 @@ int32_t dpc_profile_report(char *buf, size_t len);
  * status; this call clears it too. */
 dpc_status dpc_sync_status(void *ws, void *stream);
 
-/* Plan options of one problem (0 in any field: the library's default).  The defaults
- * also take overrides from the environment (DPC_SUBDIV, DPC_STRIP_CELLS, DPC_STAGES
- * "K:group,...", DPC_RING_CAP, DPC_GRID_DIMS, DPC_ROW_SPLIT) for tuning experiments; explicit
- * options win. */
+/* Plan options of one problem (0 in any field: the library's default).  Plans change only
+ * through these options (dpc_plan_tuned, dpc_batch_plan); every option gives the same
+ * results, bit for bit. */
 typedef struct {
   int32_t subdiv;          /* cells per cut-off distance along each axis (1..16) */
   int32_t strip_cells;     /* narrower task strips (cells along the last axis) */
   int32_t nstages;         /* dependent-search window stages (1..4), radii and groups below */
   int32_t stage_radius[4]; /* window radius of each stage in cells (1..64); 0: the density
-                              window clipped to the cut-off ball (final when closer than d_cut) */
+                              window clipped to the cut-off ball (final when closer than d_cut).
+                              Lane form runs only the first stage (a block of that radius,
+                              or the ball), then the ring search */
   int32_t stage_group[4];  /* tasks whose open points one wave gathers (1..64) */
   int32_t ring_cap;        /* most ring-search steps per point before the prefix scan */
   int32_t grid_dims;       /* coordinates the cells index (default d up to 4, else 3; d if
                               larger): the windows cover those, distances always use all d */
-  int32_t row_split;       /* density work units per task (1..window rows): parts of its rows */
+  int32_t lanes;           /* 1: tasks of 64 queries of one strip share each window's candidates
+                              (dense data); 2: one query per lane with its own window (sparse
+                              data, where a strip holds a few points); 0: the default (lanes for
+                              4-D points) */
 } dpc_tuning;
 
 /* dpc_plan with explicit options (tuning may be NULL). */

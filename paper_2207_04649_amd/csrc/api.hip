@@ -28,6 +28,8 @@ std::vector<ProfRec> g_prof_open;  // begins awaiting their end, per kernel id
 int g_prof_level = 0;
 // work counters of the last dependent search (profiling level 2)
 int64_t g_work[4] = {0, 0, 0, 0};
+// candidate distance tests of the last call's density, window search, ring search and prefix scan
+int64_t g_tests[4] = {0, 0, 0, 0};
 const char *kProfNames[kProfCount] = {"grid_build", "density", "rank_keys", "rank_sort", "search",
                                       "ringk", "peaks", "finish", "label"};
 }  // namespace
@@ -124,32 +126,6 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 // clip the windows closer to the d_cut-ball; the table grows as their power).
 int default_subdivision(int d) { return d <= 3 ? 2 : 1; }
 
-// Options from the environment (tuning experiments); 0 = not set.
-dpc_tuning env_tuning() {
-  dpc_tuning t;
-  std::memset(&t, 0, sizeof(t));
-  if (const char *env = std::getenv("DPC_SUBDIV")) t.subdiv = std::atoi(env);
-  if (const char *env = std::getenv("DPC_STRIP_CELLS")) t.strip_cells = std::atoi(env);
-  if (const char *env = std::getenv("DPC_RING_CAP")) t.ring_cap = std::atoi(env);
-  if (const char *env = std::getenv("DPC_GRID_DIMS")) t.grid_dims = std::atoi(env);
-  if (const char *env = std::getenv("DPC_ROW_SPLIT")) t.row_split = std::atoi(env);
-  if (const char *env = std::getenv("DPC_STAGES")) {  // "K:group,K:group,..."
-    int k = 0;
-    for (const char *c = env; *c && k < 4;) {
-      int K = 0, g = 1;
-      if (std::sscanf(c, "%d:%d", &K, &g) < 1) break;
-      t.stage_radius[k] = K;
-      t.stage_group[k] = g;
-      ++k;
-      c = std::strchr(c, ',');
-      if (!c) break;
-      ++c;
-    }
-    t.nstages = k;
-  }
-  return t;
-}
-
 bool valid_stages(const dpc_tuning &t) {
   if (t.nstages < 1 || t.nstages > 4) return false;
   for (int k = 0; k < t.nstages; ++k)
@@ -158,19 +134,23 @@ bool valid_stages(const dpc_tuning &t) {
   return true;
 }
 
-// Dense-table cap: at most kTableMax cells, and at most 8 per point (4096 at
-// least), so a small problem does not scan a table far larger than itself.
-int64_t table_cap(int64_t n) {
-  const int64_t c = std::max<int64_t>(4096, 8 * n);
+// Dense-table cap: at most kTableMax cells, and at most `per_point` per point
+// (4096 at least), so a small problem does not scan a table far larger than itself.
+int64_t table_cap(int64_t n, int64_t per_point) {
+  const int64_t c = std::max<int64_t>(4096, per_point * n);
   return std::min<int64_t>(kTableMax, c);
 }
+
+// Lane form (one query per lane) by default where data is sparse per cell:
+// measured on 4-D random walks, where a strip of cells holds a few points and a
+// 64-query task leaves most lanes idle.
+bool default_lanes(int d, int gm) { return d == 4 && gm == d; }
 
 bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *out) {
   if (n < 1 || n >= DPC_MAX_POINTS || d < 1 || d > DPC_MAX_DIM) return false;
   const int64_t R = cutoff_square(d_cut);
   if (R < 1) return false;
-  const dpc_tuning env = env_tuning();
-  auto pick = [&](int32_t explicit_v, int32_t env_v) { return explicit_v ? explicit_v : env_v; };
+  if (opt && (opt->lanes < 0 || opt->lanes > 2)) return false;
   Plan p;
   std::memset(&p, 0, sizeof(p));
   p.n = n;
@@ -187,19 +167,22 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   // indexed ones keep rows full (measured on blob and random-walk data).
   int gm = d <= 4 ? d : 3;
   {
-    const int v = pick(opt ? opt->grid_dims : 0, env.grid_dims);
+    const int v = opt ? opt->grid_dims : 0;
     if (v >= 1) gm = v < d ? v : d;  // more than d: all of them
   }
   p.gm = gm;
+  p.lanes = opt && opt->lanes ? (opt->lanes == 2 ? 1 : 0) : (default_lanes(d, gm) ? 1 : 0);
   // A partial grid runs the exact int64 distance path with cells one cut-off
   // wide; a full one subdivides the cut-off (finer cells clip windows closer to
-  // the ball, the table grows as their power).
-  int S = gm < d ? 1 : default_subdivision(gm);
+  // the ball, the table grows as their power).  In lane form cells are one
+  // cut-off wide: a lane's window then has 3^gm cells, and each row lookup is
+  // paid per query.
+  int S = (gm < d || p.lanes) ? 1 : default_subdivision(gm);
   {
-    const int v = pick(opt ? opt->subdiv : 0, env.subdiv);
+    const int v = opt ? opt->subdiv : 0;
     if (v >= 1 && v <= 16) S = v;
   }
-  const int64_t nc_max = iroot(table_cap(n), gm);
+  const int64_t nc_max = iroot(table_cap(n, p.lanes ? 16 : 8), gm);
   int64_t L = 1, nc = 1;
   for (;; --S) {
     L = (L0 + S - 1) / S;
@@ -233,12 +216,17 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   // task's window narrow.
   if (gm < d && p.wc > 4) p.wc = 4;
   {
-    const int64_t v = pick(opt ? opt->strip_cells : 0, env.strip_cells);
+    const int64_t v = opt ? opt->strip_cells : 0;
     if (v >= 1 && v < p.wc) p.wc = int32_t(v);  // narrower only
   }
-  // Dependent-search stages: window radii in cells and tasks gathered per wave
-  // (more as fewer points stay open); a later stage is dropped when its window
-  // has more than 4096 rows.
+  if (p.lanes) {  // the packed path needs each lane's window within E, no strips
+    p.mode = (gm == d && (int64_t(p.K0) + 1) * L <= E) ? kModeP16 : kModeI64;
+    p.wc = int32_t(nc);
+  }
+  // Dependent-search stages: window radii in cells (0: the ball stage) and, in
+  // task form, tasks gathered per wave (more as fewer points stay open); a later
+  // stage is dropped when its window has more than 4096 rows.  Lane form runs
+  // one stage (by default a block of one cell: the ring search continues from it).
   dpc_tuning st;
   std::memset(&st, 0, sizeof(st));
   st.nstages = 1;  // one window stage, then the ring search (measured best on 2-D to 6-D data)
@@ -247,9 +235,8 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   if (opt && opt->nstages) {
     if (!valid_stages(*opt)) return false;
     st = *opt;
-  } else if (env.nstages && valid_stages(env)) {
-    st = env;
   }
+  if (p.lanes) st.nstages = 1;
   p.nstages = 0;
   for (int k = 0; k < st.nstages; ++k) {
     const int K = st.stage_radius[k] == 0 ? p.K0 : st.stage_radius[k];  // 0: the ball stage
@@ -258,31 +245,24 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
     if (k > 0 && rows > 4096) break;
     p.stageK[p.nstages] = st.stage_radius[k];
     p.stageGroup[p.nstages] = st.stage_group[k];
-    p.stageMode[p.nstages] = (gm == d && p16_ok(K, p.wc)) ? kModeP16 : kModeI64;
+    // a lane's candidates lie within (K + 1) L - 1 of it in every coordinate; a
+    // task's within its strip's window
+    const bool p16 = p.lanes ? (K + 1) * L <= E : p16_ok(K, p.wc);
+    p.stageMode[p.nstages] = (gm == d && p16) ? kModeP16 : kModeI64;
     ++p.nstages;
   }
   // Ring steps before the prefix scan: more in more dimensions, where rings
   // stay cheap longer than scanning a long density prefix.
   p.ring_cap = d <= 2 ? kRingCostCap : 4 * kRingCostCap;
   {
-    const int v = pick(opt ? opt->ring_cap : 0, env.ring_cap);
+    const int v = opt ? opt->ring_cap : 0;
     if (v >= 1 && v <= 1 << 20) p.ring_cap = v;
-  }
-  // Density work units per task: by default the whole window (splitting it by
-  // rows balances the waves better, but its atomic adds and repeated task
-  // set-up cost more than they save on the measured workloads).
-  {
-    int64_t rows = 1;
-    for (int t = 0; t < gm - 1; ++t) rows *= 2 * p.K0 + 1;
-    p.row_split = 1;
-    const int v = pick(opt ? opt->row_split : 0, env.row_split);
-    if (v >= 1) p.row_split = int32_t(std::min<int64_t>(v, rows));
   }
   p.nsx = int32_t((nc + p.wc - 1) / p.wc);
   p.ncells = ipow(nc, gm);
   p.nrows = ipow(nc, gm - 1);
-  p.nstrips = p.nrows * p.nsx;
-  p.max_tasks = n / kQueryChunk + p.nstrips + 1;
+  p.nstrips = p.lanes ? 0 : p.nrows * p.nsx;  // lane form builds no strip tasks
+  p.max_tasks = p.lanes ? 0 : n / kQueryChunk + p.nstrips + 1;
 
   const int64_t scan_max = std::max(std::max(p.ncells + 1, p.nstrips + 1), n + 1);
   size_t o = 0;
@@ -292,7 +272,10 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
     return at;
   };
   p.o_hdr = take(sizeof(DevHeader));
-  p.o_cnt = take(size_t(p.ncells + 1) * 4);
+  // the cell table, with three slack entries after it: a radius-1 lane window
+  // reads start[x - 1 .. x + 2] of a row in one load (start[-1] is the last word
+  // of the header slot just before the table; neither slack value is used)
+  p.o_cnt = take(size_t(p.ncells + 1 + 3) * 4);
   p.o_bsum = take(size_t(scan_max / kScanTile + 2) * 4);
   p.o_key = take(size_t(n) * 4);
   p.o_slot = take(size_t(n) * 4);
@@ -309,6 +292,8 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   p.o_unres = take(size_t(n + 1) * 4);  // + a spare slot for lanes that append nothing
   p.o_peaks = take(size_t(n + 1) * 4);
   p.o_flag = take(size_t(n));
+  p.o_srec = 0;
+  if (p.lanes && d <= 4 && p.stageMode[0] == kModeP16) p.o_srec = take(size_t(n) * 16);
   p.total = o;
   *out = p;
   return true;
@@ -322,18 +307,43 @@ dpc_status check_common(const int32_t *pts, int64_t n, int32_t d, double d_cut, 
   if (!std::isfinite(d_cut) || !(d_cut > 0.0)) return fail(DPC_EINVAL, "d_cut must be finite and > 0");
   if (!make_plan(n, d, d_cut, nullptr, p)) return fail(DPC_EINVAL, "no plan for these sizes");
   if (ws_bytes < p->total) return fail(DPC_EWORKSPACE, "workspace smaller than dpc_workspace_bytes()");
+  p->count_work = g_prof_level >= 2 ? 1 : 0;
   return DPC_OK;
 }
 
-dpc_status run_density(const Plan &p, const Ws &w, const int32_t *pts, int32_t *rho, hipStream_t s) {
+// 64-bit FNV-1a of a plan's bytes (the struct is zero-filled before its fields
+// are set, so equal plans hash equally).
+uint64_t plan_hash(const Plan &plan) {
+  Plan p = plan;
+  p.count_work = 0;  // profiling does not change the grid
+  const unsigned char *b = reinterpret_cast<const unsigned char *>(&p);
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < sizeof(Plan); ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+// The identity of the grid a call on these inputs builds.
+GridStamp grid_stamp(const Plan &p, const int32_t *pts) {
+  GridStamp st;
+  st.w[0] = kStampMagic;
+  st.w[1] = uint64_t(reinterpret_cast<uintptr_t>(pts));
+  st.w[2] = uint64_t(p.n);
+  st.w[3] = uint64_t(p.R);
+  st.w[4] = plan_hash(p);
+  st.w[5] = uint64_t(p.d) | (uint64_t(p.gm) << 8) | (uint64_t(p.lanes) << 16) | (uint64_t(uint32_t(p.L)) << 32);
+  return st;
+}
+
+// Grid and local density; the density stays in the workspace's rank keys.
+dpc_status run_density(const Plan &p, const Ws &w, const int32_t *pts, hipStream_t s) {
   hipError_t e;
   {
     ProfScope ps(s, kProfGrid);
-    e = build_grid(p, w, pts, s);
+    e = build_grid(p, w, pts, grid_stamp(p, pts), s);
   }
   if (e != hipSuccess) return device_fail(e, "grid build");
   ProfScope ps(s, kProfDensity);
-  e = launch_density(p, w, rho, s);
+  e = launch_density(p, w, s);
   if (e != hipSuccess) return device_fail(e, "density kernel");
   return DPC_OK;
 }
@@ -358,27 +368,38 @@ hipError_t record_work(const Plan &p, const Ws &w, hipStream_t s) {
   g_work[1] = h.n_unres;
   g_work[2] = h.n_peaks;
   g_work[3] = prefix;
+  for (int k = 0; k < 4; ++k) g_tests[k] = int64_t(h.work[k]);
   return hipSuccess;
 }
 
-dpc_status run_dependent(const Plan &p, const Ws &w, const int32_t *pts, const int32_t *rho, int32_t *dep,
-                         double *delta, bool reuse, hipStream_t s) {
+// Dependent points.  `rho_in` (caller's densities, id order) fills the rank keys,
+// or, when null, the keys the density kernel left in the workspace are used and
+// `rho_out` receives the densities in id order.  The grid is built (kGridBuild),
+// taken from a previous dpc_density call on the same workspace after checking
+// its stamp on the device (kGridReuse), or built earlier in the same call
+// (kGridOwn).
+enum GridSource { kGridBuild, kGridReuse, kGridOwn };
+
+dpc_status run_dependent(const Plan &p, const Ws &w, const int32_t *pts, const int32_t *rho_in, int32_t *dep,
+                         double *delta, int32_t *rho_out, GridSource grid, hipStream_t s) {
   hipError_t e;
-  if (!reuse) {
+  if (grid == kGridBuild) {
     ProfScope ps(s, kProfGrid);
-    if ((e = build_grid(p, w, pts, s)) != hipSuccess) return device_fail(e, "grid build");
+    if ((e = build_grid(p, w, pts, grid_stamp(p, pts), s)) != hipSuccess) return device_fail(e, "grid build");
+  } else if (grid == kGridReuse) {
+    if ((e = check_grid(w.hdr, grid_stamp(p, pts), s)) != hipSuccess) return device_fail(e, "grid check");
   } else if ((e = reset_counters(w.hdr, false, s)) != hipSuccess) {
     return device_fail(e, "reset");
   }
-  {
+  if (rho_in) {
     ProfScope ps(s, kProfRankKeys);
-    if ((e = gather_rank_keys(p, w, rho, s)) != hipSuccess) return device_fail(e, "rank keys");
+    if ((e = gather_rank_keys(p, w, rho_in, s)) != hipSuccess) return device_fail(e, "rank keys");
   }
   {
     ProfScope ps(s, kProfRankSort);
     if ((e = rank_sort(p, w, s)) != hipSuccess) return device_fail(e, "rank sort");
   }
-  if ((e = launch_dependent(p, w, dep, delta, s)) != hipSuccess) return device_fail(e, "dependent kernels");
+  if ((e = launch_dependent(p, w, dep, delta, rho_out, s)) != hipSuccess) return device_fail(e, "dependent kernels");
   if (g_prof_level >= 2 && (e = record_work(p, w, s)) != hipSuccess) return device_fail(e, "work counters");
   return DPC_OK;
 }
@@ -396,6 +417,7 @@ void fill_plan_info(const Plan &p, dpc_plan_info *out) {
   out->window_radius = p.K0;
   out->stages = p.nstages;
   out->grid_dims = p.gm;
+  out->lanes = p.lanes;
 }
 
 dpc_status check_job(const dpc_job &j) {
@@ -536,8 +558,11 @@ dpc_status dpc_batch_plan(const dpc_job *jobs, int32_t njobs, const dpc_tuning *
     add_blocks(b->maps[kMapCells], uint32_t(k), (p.ncells + kBatchCells) / kBatchCells);
     add_blocks(b->maps[kMapStrips], uint32_t(k), (p.nstrips + kBatchPoints) / kBatchPoints);
     const uint32_t w0 = uint32_t(b->maps[kMapWork].vjob.size());
+    // persistent work: about kBatchTasks tasks per virtual block, or in lane form
+    // kBatchLanePoints points (kBlock lanes, a few points each)
     add_blocks(b->maps[kMapWork], uint32_t(k),
-               std::min<int64_t>(2048, (p.max_tasks * p.row_split + kBatchTasks - 1) / kBatchTasks));
+               p.lanes ? (p.n + kBatchLanePoints - 1) / kBatchLanePoints
+                       : std::min<int64_t>(2048, (p.max_tasks + kBatchTasks - 1) / kBatchTasks));
     if (b->ngroups == 0 || b->gdim[b->ngroups - 1] != p.d) {
       b->gdim[b->ngroups] = p.d;
       b->gwork0[b->ngroups] = w0;
@@ -670,9 +695,12 @@ dpc_status dpc_density(const int32_t *pts, int64_t n, int32_t d, double d_cut, i
   if (st != DPC_OK) return st;
   if (!rho) return fail(DPC_EINVAL, "null pointer argument");
   const Ws w = resolve(p, ws);
-  hipError_t e = clear_status(w.hdr, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = clear_status(w.hdr, s);
   if (e != hipSuccess) return device_fail(e, "status reset");
-  return run_density(p, w, pts, rho, static_cast<hipStream_t>(stream));
+  if ((st = run_density(p, w, pts, s)) != DPC_OK) return st;
+  e = write_rho(p, w, rho, s);
+  return e == hipSuccess ? DPC_OK : device_fail(e, "density output");
 }
 
 dpc_status dpc_dependent(const int32_t *pts, int64_t n, int32_t d, double d_cut, const int32_t *rho,
@@ -683,9 +711,15 @@ dpc_status dpc_dependent(const int32_t *pts, int64_t n, int32_t d, double d_cut,
   if (!rho || !dep || !delta) return fail(DPC_EINVAL, "null pointer argument");
   if (flags & ~DPC_REUSE_GRID) return fail(DPC_EINVAL, "unknown flag");
   const Ws w = resolve(p, ws);
-  hipError_t e = clear_status(w.hdr, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return device_fail(e, "status reset");
-  return run_dependent(p, w, pts, rho, dep, delta, (flags & DPC_REUSE_GRID) != 0, static_cast<hipStream_t>(stream));
+  const bool reuse = (flags & DPC_REUSE_GRID) != 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // A reused grid keeps the status of its build (a clamped coordinate); the grid
+  // check clears the rest.
+  if (!reuse) {
+    hipError_t e = clear_status(w.hdr, s);
+    if (e != hipSuccess) return device_fail(e, "status reset");
+  }
+  return run_dependent(p, w, pts, rho, dep, delta, nullptr, reuse ? kGridReuse : kGridBuild, s);
 }
 
 dpc_status dpc_label(int64_t n, const int32_t *rho, const int32_t *dep, const double *delta, int32_t rho_min,
@@ -718,8 +752,8 @@ dpc_status dpc_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32
   const Ws w = resolve(p, ws);
   hipError_t e0 = clear_status(w.hdr, s);
   if (e0 != hipSuccess) return device_fail(e0, "status reset");
-  if ((st = run_density(p, w, pts, rho, s)) != DPC_OK) return st;
-  if ((st = run_dependent(p, w, pts, rho, dep, delta, true, s)) != DPC_OK) return st;
+  if ((st = run_density(p, w, pts, s)) != DPC_OK) return st;
+  if ((st = run_dependent(p, w, pts, nullptr, dep, delta, rho, kGridOwn, s)) != DPC_OK) return st;
   ProfScope ps(s, kProfLabel);
   hipError_t e = launch_label(n, rho, dep, delta, rho_min, delta_min, label, ncenters, w.hdr, s);
   if (e != hipSuccess) return device_fail(e, "label kernels");
@@ -756,11 +790,14 @@ int32_t dpc_profile_report(char *buf, size_t len) {
     out += item;
   }
   {
-    char item[192];
+    char item[512];
     std::lock_guard<std::mutex> lk(g_prof_mu);
     std::snprintf(item, sizeof(item), ", \"work\": {\"tasks\": %lld, \"open\": %lld, \"peaks\": %lld, "
-                  "\"peak_prefix\": %lld}", static_cast<long long>(g_work[0]), static_cast<long long>(g_work[1]),
-                  static_cast<long long>(g_work[2]), static_cast<long long>(g_work[3]));
+                  "\"peak_prefix\": %lld, \"tests_density\": %lld, \"tests_search\": %lld, \"tests_ring\": %lld, "
+                  "\"tests_peaks\": %lld}", static_cast<long long>(g_work[0]), static_cast<long long>(g_work[1]),
+                  static_cast<long long>(g_work[2]), static_cast<long long>(g_work[3]),
+                  static_cast<long long>(g_tests[0]), static_cast<long long>(g_tests[1]),
+                  static_cast<long long>(g_tests[2]), static_cast<long long>(g_tests[3]));
     out += item;
   }
   out += "}";

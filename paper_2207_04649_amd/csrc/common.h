@@ -24,6 +24,8 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kBatchPoints = 4096;       // points (or strips) per virtual block of a many-job launch
 constexpr int kBatchCells = 8192;        // table cells per virtual block of a many-job launch
 constexpr int kBatchTasks = 8;           // tasks per virtual block of the persistent kernels
+constexpr int kBatchLanePoints = 1024;   // points per virtual block of lane-form kernels
+enum WorkCounter { kWorkDensity = 0, kWorkSearch, kWorkRing, kWorkPeaks };
 constexpr int kPeakChunk = 256;          // rank-order candidates per prefix-scan work unit
 constexpr int64_t kGridCap = 32768;      // most workgroups of a wave-task launch (16 x the resident 2048)
 constexpr int kRingCostCap = 48;         // default of Plan::ring_cap
@@ -34,13 +36,23 @@ enum DistMode : int32_t {
   kModeI64 = 1,  // exact int64 squared distances on full coordinates
 };
 
+// Identity of the grid a workspace holds: written by the grid build, checked by a
+// dependent-point search that reuses the grid (DPC_REUSE_GRID).
+constexpr int kStampWords = 6;
+constexpr uint64_t kStampMagic = 0x44504347524944ull;  // "DPCGRID"
+
 // Device-side scalars of one workspace.  Counters are reset by the call that uses them.
 struct DevHeader {
   uint32_t status;        // errors of the current call: bit 0 coordinate out of range, bit 1 inconsistent input
   uint32_t ntasks;        // tasks of the density and search kernels (written by the task builder)
   uint32_t n_unres;       // points left open by the search stages
   uint32_t n_peaks;       // points left to the rank-prefix scan
-  uint32_t pad[60];
+  uint32_t skip;          // 1: the workspace holds no grid of this call's inputs; grid kernels do nothing
+  uint32_t pad0;
+  uint64_t stamp[kStampWords];  // the grid's identity (grid_stamp)
+  uint64_t work[4];       // with Plan::count_work: candidate (query, point) distance tests of the
+                          // density, window search, ring search and prefix scan kernels
+  uint32_t pad[38];
 };
 static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
 
@@ -63,14 +75,16 @@ struct Plan {
   int32_t stageMode[4];  // DistMode of each stage
   int32_t ring_cap;  // most ring-search steps per point before the prefix scan
   int32_t gm;        // grid dimensions: the cells index the first gm coordinates (1..d)
-  int32_t row_split; // density work units per task: its window rows in this many parts
+  int32_t lanes;     // 1: one query per lane with its own window (sparse data); 0: tasks of 64
+                     // queries of one strip sharing a window's candidates (dense data)
+  int32_t count_work; // 1: the kernels count their distance tests into DevHeader::work (profiling)
   int64_t ncells;    // nc^gm
   int64_t nrows;     // nc^(gm-1)
   int64_t nstrips;   // nrows * nsx
   int64_t max_tasks;
   // workspace byte offsets
   size_t o_hdr, o_cnt, o_bsum, o_key, o_slot, o_spts, o_spk, o_sid, o_sK, o_tcnt, o_tasks, o_rcnt,
-      o_rpts, o_rid, o_best, o_unres, o_peaks, o_flag, total;
+      o_rpts, o_rid, o_best, o_unres, o_peaks, o_flag, o_srec, total;
 };
 
 // Pointers into one workspace, resolved from a Plan.
@@ -78,21 +92,25 @@ struct Ws {
   DevHeader *hdr;
   uint32_t *cnt;     // [ncells + 1] cell counts, then cell starts (exclusive scan)
   uint32_t *bsum;    // scan block sums
-  uint32_t *key;     // [n] cell key per id
+  uint32_t *key;     // [n] cell key per id; after the id scatter, the id's cell-order position
   uint32_t *slot;    // [n] slot within the cell (later: slot within the rho bucket)
   int32_t *spts;     // [n][d] clamped coordinates in cell order
   uint32_t *spk;     // [n][words] packed low 16 bits of the coordinates, cell order
   int32_t *sid;      // [n] id at each cell-order position
-  uint64_t *sK;      // [n] (rho << 32) | ~id at each cell-order position
+  uint64_t *sK;      // [n] (rho << 32) | ~id at each cell-order position (written by the
+                     // density kernels, or gathered from a caller's rho)
   uint32_t *tcnt;    // [nstrips + 1] tasks per strip, then task offsets
   uint4 *tasks;      // [max_tasks] {first query, end query, strip, 0}
   uint32_t *rcnt;    // [n + 1] rho histogram by (n - rho), then bucket starts
   int32_t *rpts;     // [n][d] coordinates in rank order
   int32_t *rid;      // [n] id at each rank position
-  uint64_t *best;    // [n] packed (D2 << 27 | dep) per id, kNoKey if none
+  uint64_t *best;    // [n] packed (D2 << 27 | dep) per cell-order position, kNoKey if none
   uint32_t *unres;   // [n + 1] cell-order positions open after the search stages (+ spare slot)
   uint32_t *peaks;   // [n + 1] cell-order positions left to the rank-prefix scan (+ spare slot)
   uint8_t *flag;     // [n] 1 while the cell-order position's dependent point is open
+  uint4 *srec;       // [n] lane form with packed coordinates of d <= 4: per cell-order position
+                     // {packed words (one or two), rank key low, rank key high}, what a lane
+                     // search reads of a candidate in one 16-byte load (null otherwise)
 };
 
 inline Ws resolve(const Plan &p, void *base) {
@@ -116,6 +134,7 @@ inline Ws resolve(const Plan &p, void *base) {
   w.unres = reinterpret_cast<uint32_t *>(b + p.o_unres);
   w.peaks = reinterpret_cast<uint32_t *>(b + p.o_peaks);
   w.flag = reinterpret_cast<uint8_t *>(b + p.o_flag);
+  w.srec = p.o_srec ? reinterpret_cast<uint4 *>(b + p.o_srec) : nullptr;
   return w;
 }
 
@@ -163,14 +182,27 @@ inline unsigned vgrid(const VMap &m) {
   return v < uint32_t(kGridCap) ? v : uint32_t(kGridCap);
 }
 
+// The identity a grid build stamps into its workspace header.
+struct GridStamp {
+  uint64_t w[kStampWords];
+};
+
 // Host-side launch helpers (implemented in the .hip files).
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_scan(uint32_t *data, int64_t count, uint32_t *bsum, hipStream_t s);
-hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, hipStream_t s);
+// Grid: cell keys, counting sort into cells, cell-order copies, strip tasks; stamps the header.
+hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, const GridStamp &stamp, hipStream_t s);
+// Checks the header's stamp against `stamp` (a reused grid): on a mismatch every grid kernel
+// of the call does nothing and the status gets the inconsistent-input bit.
+hipError_t check_grid(DevHeader *hdr, const GridStamp &stamp, hipStream_t s);
+// Rank keys of the cell-order positions from a caller's densities (id order).
 hipError_t gather_rank_keys(const Plan &p, const Ws &w, const int32_t *rho, hipStream_t s);
-hipError_t launch_density(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s);
+// Local density into the rank keys (cell order); write_rho copies it to the caller's id order.
+hipError_t launch_density(const Plan &p, const Ws &w, hipStream_t s);
+hipError_t write_rho(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s);
 hipError_t rank_sort(const Plan &p, const Ws &w, hipStream_t s);
-hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, hipStream_t s);
+// Dependent points; the outputs (and rho, if not null) are written in id order.
+hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, int32_t *rho, hipStream_t s);
 hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const double *delta,
                         int32_t rho_min, double delta_min, int32_t *label, int64_t *ncenters,
                         DevHeader *hdr, hipStream_t s);
@@ -278,6 +310,33 @@ struct Blk {
 };
 
 __device__ __forceinline__ Blk grid_blk() { return Blk{blockIdx.x, gridDim.x}; }
+
+// The launch's blocks renumbered so that the blocks of each XCD cover one
+// contiguous run: the dispatcher hands workgroups to the 8 XCDs in turn (block b
+// to XCD b % 8), and each XCD has its own L2, so work that reads neighbouring
+// cell-order data shares that cache when it runs on one XCD.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ Blk xcd_blk() {
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t per = nb / kXcds, rem = nb % kXcds, x = b % kXcds, i = b / kXcds;
+  return Blk{x * per + (x < rem ? x : rem) + i, nb};
+}
+
+// Adds a lane's count of distance tests to a work counter (profiling): a wave
+// sum, then one atomic by the first lane.  Call it where every lane of the wave
+// is active (after the kernel's work loop), and only when the count is wanted.
+__device__ __forceinline__ void add_work(dpc::DevHeader *hdr, int which, uint64_t lane_count) {
+  uint64_t v = lane_count;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, dpc::kWave);
+  if (lane_id() == 0 && v) atomicAdd(reinterpret_cast<unsigned long long *>(&hdr->work[which]), (unsigned long long)v);
+}
+
+// True when the call found no grid of its inputs in the workspace (check_grid):
+// the kernels that index the grid's arrays then return at once.
+__device__ __forceinline__ bool grid_skipped(const dpc::DevHeader *hdr) {
+  return uniform(uint32_t(as_const(&hdr->skip)[0])) != 0u;
+}
 
 // Index of the calling wave among the job's waves, and their number: wave loops
 // take items wave_index(k), wave_index(k) + grid_waves(k), ...  A static

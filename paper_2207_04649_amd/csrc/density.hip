@@ -1,26 +1,29 @@
 // Local density (Def. 1, Eq. 1): rho_i = #{ j : D2(i, j) < R }, the point itself
-// included, R = ceil(d_cut^2).
+// included, R = ceil(d_cut^2).  The count goes into the rank key (rho << 32) | ~id
+// of the point's cell-order position (contiguous stores); write_rho copies it to
+// the caller's id order, reading the cell-order array at each id's position.
 //
-// One wave per task (64 queries, one per lane).  The window holds the cells
-// within K0 of the task's cells (K0 * L >= floor(sqrt(R - 1)), so it covers every
-// d_cut-ball) and is clipped to the balls' union row by row.  The wave walks its
-// candidate runs with scalar loads, so every candidate reaches all 64 lanes as a
-// scalar operand: no LDS, no barriers.
+// Two forms, picked by the plan:
 //
-// Work units are (task, part of its window rows): a dense task's window holds
-// thousands of candidates, so whole tasks leave a few waves with several times
-// the average work.  With more than one part per task, every part adds its
-// counts into rho with an atomic add (rho cleared first); with one, the count is
-// stored.  Waves take units in a static interleave (see wave_index); the paper
-// balances the per-point range searches with dynamic OpenMP scheduling
-// (Section 3), the interleave does it in these smaller units.
+// * tasks (dense data): one wave per task (64 queries of one strip, one per
+//   lane).  The window holds the cells within K0 of the task's cells (K0 * L >=
+//   floor(sqrt(R - 1)), so it covers every d_cut-ball) and is clipped to the
+//   balls' union row by row.  The wave walks its candidate runs with scalar
+//   loads, so every candidate reaches all 64 lanes as a scalar operand: no LDS,
+//   no barriers.  Waves take tasks in a static interleave (see wave_index); the
+//   paper balances its per-point range searches with dynamic OpenMP scheduling
+//   (Section 3);
+// * lanes (sparse data, where a strip holds a few points and a task would leave
+//   most lanes idle): one query per lane, each with its own window of radius K0
+//   around its cell, clipped to its own ball row by row; candidates are read with
+//   per-lane vector loads.
 #include "tasks.h"
 
 namespace dpc {
 namespace {
 
 template <int D, int MODE>
-__device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w, int32_t *__restrict__ rho) {
+__device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w) {
   constexpr int W = (D + 1) / 2;
   const int lane = lane_id();
   DPC_CONST(uint32_t) *spk = as_const(w.spk);
@@ -32,15 +35,10 @@ __device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w
   const uint64_t clip2 = uint64_t(p.R - 1);  // D2 <= R - 1 is inside the ball
   const int nrow = int(window_rows(p, K));
 
-  const uint32_t parts = uint32_t(p.row_split);
-  const int rows_per = (nrow + int(parts) - 1) / int(parts);
-  const uint64_t units = uint64_t(ntasks) * parts;
-
+  uint64_t work = 0;  // candidate tests of the wave's valid queries (profiling)
   const uint32_t nw = grid_waves(blk);
-  for (uint64_t u = wave_index(blk); u < units; u += nw) {
-    const uint32_t t = uint32_t(u / parts);
-    const int r_lo = int(u % parts) * rows_per;
-    const int r_hi = min(nrow, r_lo + rows_per);
+  for (uint32_t t = wave_index(blk); t < ntasks; t += nw) {
+    const int r_lo = 0, r_hi = nrow;
     const uint32_t qb = uniform(uint32_t(tc[4 * int64_t(t)]));
     const uint32_t qe = uniform(uint32_t(tc[4 * int64_t(t) + 1]));
     TaskGeom<D> g;
@@ -63,6 +61,7 @@ __device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w
       for (int r = 0; r < nr; ++r) {
         const uint32_t b = __builtin_amdgcn_readlane(sb, r);
         const uint32_t e = __builtin_amdgcn_readlane(se, r);
+        work += uint64_t(e - b) * (qe - qb);
         uint32_t j = b;
         if (MODE == kModeP16) {
           // B candidates per batch: one scalar load per 16 words.  (Double
@@ -102,36 +101,108 @@ __device__ __forceinline__ void density_body(Blk blk, const Plan &p, const Ws &w
       }
     }
     // Lanes past the end of the task repeat its last query: they store the same
-    // value, or add 0, so no lane-divergent branch surrounds the store.
-    const int32_t id = w.sid[q];
-    if (parts == 1)
-      rho[id] = int32_t(count);
-    else
-      atomicAdd(&rho[id], qb + uint32_t(lane) < qe ? int32_t(count) : 0);
+    // value, so no lane-divergent branch surrounds the store.
+    w.sK[q] = (uint64_t(count) << 32) | uint32_t(~uint32_t(w.sid[q]));
   }
+  if (p.count_work) add_work(w.hdr, kWorkDensity, lane == 0 ? work : 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_zero_i32(int32_t *__restrict__ v, int64_t n) {
-  for (int64_t i = thread_index(grid_blk()); i < n; i += grid_threads(grid_blk())) v[i] = 0;
-}
 
-// rho of every job that splits its density tasks, cleared for the atomic adds.
-__global__ __launch_bounds__(kBlock) void kb_zero_rho(const JobDev *jobs, VMap m) {
-  for (uint32_t v = m.v0 + blockIdx.x; v < m.v1; v += gridDim.x) {
-    const uint32_t j = vjob_of(m, v);
-    const Blk k = vblk_of(m, v, j);
-    if (uniform(int32_t(as_const(jobs)[j].p.row_split)) > 1) {
-      const int64_t n = as_const(jobs)[j].p.n;
-      int32_t *rho = as_const(jobs)[j].rho;
-      for (int64_t i = thread_index(k); i < n; i += grid_threads(k)) rho[i] = 0;
+// One query per lane: the cells within K0 of the query's own cell, clipped to
+// its ball row by row (a row farther than d_cut is skipped; in the strip
+// dimension a cell is kept when its nearest coordinate is within d_cut).
+template <int D, int MODE>
+__device__ __forceinline__ void density_lanes(Blk blk, const Plan &p, const Ws &w) {
+  constexpr int W = (D + 1) / 2;
+  const int32_t negR = -int32_t(p.R < INT32_MAX ? p.R : INT32_MAX);
+  const int64_t R1 = p.R - 1;  // D2 <= R - 1 is inside the ball
+  const int K = p.K0;
+  const int nrow = int(window_rows(p, K));
+  uint64_t work = 0;  // the lane's candidate tests (profiling)
+  for (int64_t q = thread_index(blk); q < p.n; q += grid_threads(blk)) {
+    LaneGeom<D> g;
+    lane_geom<D>(p, w.spts + q * D, g);
+    uint32_t qk[W];
+    if (MODE == kModeP16) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) qk[k] = w.spk[q * W + k];
     }
+    uint32_t count = 0;
+    // one candidate: inside the ball or not
+    auto test = [&](uint32_t j) {
+      if (MODE == kModeP16) {
+        uint32_t cw[W];
+        load_words<W>(w.spk + int64_t(j) * W, cw);
+        int32_t acc = dot2_self_v(pk_sub16(qk[0], cw[0]), negR);
+#pragma unroll
+        for (int k = 1; k < W; ++k) acc = dot2_self_v(pk_sub16(qk[k], cw[k]), acc);
+        count += uint32_t(acc) >> 31;
+      } else {
+        int64_t d2 = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const int64_t df = int64_t(g.x[k] - w.spts[int64_t(j) * D + k]);
+          d2 += df * df;
+        }
+        count += d2 <= R1 ? 1u : 0u;
+      }
+    };
+    bool done = false;
+    if constexpr (D <= 4) {
+      if (K == 1 && p.gm == D) {  // compile-time rows (3^(D-1) of them)
+        auto visit = [&](uint32_t b, uint32_t e) {
+          work += e - b;
+          for (uint32_t j = b; j < e; ++j) test(j);
+        };
+        if (MODE == kModeP16)
+          walk_k1<D, uint32_t>(p, g, w.cnt, [&]() { return uint32_t(R1); }, visit);
+        else
+          walk_k1<D, int64_t>(p, g, w.cnt, [&]() { return R1; }, visit);
+        done = true;
+      }
+    }
+    if (!done) {
+      RowWalk<D> rw(K, false);
+      for (int r0 = 0; r0 < nrow; r0 += kLaneRowChunk) {
+        // cell ranges of the chunk's rows first (independent loads), then their candidates
+        uint32_t bb[kLaneRowChunk], ee[kLaneRowChunk];
+#pragma unroll
+        for (int c = 0; c < kLaneRowChunk; ++c) {
+          bb[c] = ee[c] = 0;
+          if (r0 + c < nrow) lane_row<D>(p, g, rw, K, R1, w.cnt, &bb[c], &ee[c]);
+          rw.next(p, K);
+        }
+#pragma unroll
+        for (int c = 0; c < kLaneRowChunk; ++c) {
+          work += ee[c] - bb[c];
+          for (uint32_t j = bb[c]; j < ee[c]; ++j) test(j);
+        }
+      }
+    }
+    const uint64_t key = (uint64_t(count) << 32) | uint32_t(~uint32_t(w.sid[q]));
+    w.sK[q] = key;
+    if (MODE == kModeP16 && W <= 2 && w.srec)
+      w.srec[q] = make_uint4(qk[0], W == 2 ? qk[W - 1] : 0u, uint32_t(key), uint32_t(key >> 32));
   }
+  if (p.count_work) add_work(w.hdr, kWorkDensity, work);
+}
+
+// The caller's rho in id order: each id reads its cell-order position's key.
+__device__ __forceinline__ void rho_out(Blk blk, const Plan &p, const Ws &w, int32_t *__restrict__ rho) {
+  for (int64_t i = thread_index(blk); i < p.n; i += grid_threads(blk)) rho[i] = int32_t(w.sK[w.key[i]] >> 32);
 }
 
 template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w, int32_t *__restrict__ rho) {
-  density_body<D, MODE>(grid_blk(), p, w, rho);
+__global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w) {
+  density_body<D, MODE>(grid_blk(), p, w);
 }
+
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_density_lanes(Plan p, Ws w) {
+  density_lanes<D, MODE>(xcd_blk(), p, w);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rho_out(Plan p, Ws w, int32_t *rho) { rho_out(grid_blk(), p, w, rho); }
 
 // Many-job form: the jobs of one dimension, each on its own virtual blocks.
 template <int D>
@@ -141,20 +212,34 @@ __global__ __launch_bounds__(kBlock) void kb_density(const JobDev *jobs, VMap m)
     const Blk k = vblk_of(m, v, j);
     const Plan p = load_uniform(&jobs[j].p);
     const Ws w = load_uniform(&jobs[j].w);
-    int32_t *rho = as_const(jobs)[j].rho;
-    if (p.mode == kModeP16)
-      density_body<D, kModeP16>(k, p, w, rho);
-    else
-      density_body<D, kModeI64>(k, p, w, rho);
+    if (p.lanes) {
+      if (p.mode == kModeP16)
+        density_lanes<D, kModeP16>(k, p, w);
+      else
+        density_lanes<D, kModeI64>(k, p, w);
+    } else if (p.mode == kModeP16) {
+      density_body<D, kModeP16>(k, p, w);
+    } else {
+      density_body<D, kModeI64>(k, p, w);
+    }
   }
 }
 
 template <int D>
-hipError_t launch_d(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s, unsigned blocks) {
+hipError_t launch_d(const Plan &p, const Ws &w, hipStream_t s) {
+  if (p.lanes) {
+    const unsigned blocks = blocks_for(p.n, kBlock);
+    if (p.mode == kModeP16)
+      DPC_LAUNCH((k_density_lanes<D, kModeP16>), blocks, kBlock, s, p, w);
+    else
+      DPC_LAUNCH((k_density_lanes<D, kModeI64>), blocks, kBlock, s, p, w);
+    return hipGetLastError();
+  }
+  const unsigned blocks = persistent_blocks(p.max_tasks);
   if (p.mode == kModeP16)
-    DPC_LAUNCH((k_density<D, kModeP16>), blocks, kBlock, s, p, w, rho);
+    DPC_LAUNCH((k_density<D, kModeP16>), blocks, kBlock, s, p, w);
   else
-    DPC_LAUNCH((k_density<D, kModeI64>), blocks, kBlock, s, p, w, rho);
+    DPC_LAUNCH((k_density<D, kModeI64>), blocks, kBlock, s, p, w);
   return hipGetLastError();
 }
 
@@ -172,24 +257,26 @@ unsigned persistent_blocks(int64_t max_items) {
   return static_cast<unsigned>(blocks < kGridCap ? blocks : kGridCap);
 }
 
-hipError_t launch_density(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s) {
-  if (p.row_split > 1) DPC_LAUNCH((k_zero_i32), blocks_for(p.n, kBlock * 4), kBlock, s, rho, p.n);
-  const unsigned blocks = persistent_blocks(p.max_tasks * p.row_split);
+hipError_t launch_density(const Plan &p, const Ws &w, hipStream_t s) {
   switch (p.d) {
-    case 1: return launch_d<1>(p, w, rho, s, blocks);
-    case 2: return launch_d<2>(p, w, rho, s, blocks);
-    case 3: return launch_d<3>(p, w, rho, s, blocks);
-    case 4: return launch_d<4>(p, w, rho, s, blocks);
-    case 5: return launch_d<5>(p, w, rho, s, blocks);
-    case 6: return launch_d<6>(p, w, rho, s, blocks);
-    case 7: return launch_d<7>(p, w, rho, s, blocks);
-    case 8: return launch_d<8>(p, w, rho, s, blocks);
+    case 1: return launch_d<1>(p, w, s);
+    case 2: return launch_d<2>(p, w, s);
+    case 3: return launch_d<3>(p, w, s);
+    case 4: return launch_d<4>(p, w, s);
+    case 5: return launch_d<5>(p, w, s);
+    case 6: return launch_d<6>(p, w, s);
+    case 7: return launch_d<7>(p, w, s);
+    case 8: return launch_d<8>(p, w, s);
     default: return hipErrorInvalidValue;
   }
 }
 
+hipError_t write_rho(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s) {
+  DPC_LAUNCH((k_rho_out), blocks_for(p.n, kBlock), kBlock, s, p, w, rho);
+  return hipGetLastError();
+}
+
 hipError_t batch_density(const BatchMaps &B, hipStream_t s) {
-  if (vgrid(B.pts)) DPC_LAUNCH((kb_zero_rho), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   for (int g = 0; g < B.ngroups; ++g) {
     VMap m = B.work;
     m.v0 = B.gwork0[g];

@@ -37,7 +37,7 @@ namespace {
 // than d_cut to each query; a point is final when its best is inside its ball.
 template <int D, int MODE>
 __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int Kin, bool first, uint32_t strip,
-                                             uint32_t q, bool valid) {
+                                             uint32_t q, bool valid, uint64_t *work) {
   const bool ball = Kin == 0;
   const int K = ball ? p.K0 : Kin;
   constexpr int W = (D + 1) / 2;
@@ -53,8 +53,7 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int Kin
   for (int k = 0; k < D; ++k) qx[k] = w.spts[int64_t(q) * D + k];
   task_span<D>(p, g, w.spts[int64_t(q) * D + (p.gm - 1)], valid);  // strip-dimension coordinate
   const uint64_t Ki = w.sK[q];
-  const uint32_t id = uint32_t(~uint32_t(Ki));
-  uint64_t best = first ? kNoKey : w.best[id];
+  uint64_t best = first ? kNoKey : w.best[q];
   // Clip the window to the largest best distance when every point has one.
   const bool all_have = __ballot(valid && best == kNoKey) == 0;
   uint64_t clip2 = ball ? uint64_t(p.R - 1) : ~uint64_t(0);
@@ -70,6 +69,7 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int Kin
     if (best != kNoKey) best = ((best >> kIdBits) << 32) | (best & kIdMask);
   }
   const int nrow = int(window_rows(p, K));
+  const uint32_t nvalid = uint32_t(__popcll(__ballot(valid)));
   for (int rb = 0; rb < nrow; rb += kWave) {
     uint32_t sb = 0, se = 0;
     if (rb + lane < nrow) window_row<D>(p, g, K, rb + lane, clip2, w.cnt, &sb, &se);
@@ -77,6 +77,7 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int Kin
     for (int r = 0; r < nr; ++r) {
       const uint32_t b = __builtin_amdgcn_readlane(sb, r);
       const uint32_t e = __builtin_amdgcn_readlane(se, r);
+      *work += uint64_t(e - b) * nvalid;
       uint32_t j = b;
       if (MODE == kModeP16) {
         constexpr int B = 8 / W > 0 ? 8 / W : 1;
@@ -130,8 +131,124 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int Kin
   const uint64_t ext = window_exterior_d2<D>(p, g, K, qx);
   const uint64_t bound = ball ? uint64_t(p.R) : ext;  // every point closer than this was searched
   const bool resolved = ext == kNoKey || (best != kNoKey && (best >> kIdBits) < bound);
-  w.best[id] = best;
+  w.best[q] = best;
   w.flag[q] = resolved ? 0 : 1;
+}
+
+// ------------------------------------------------------------ lane form
+//
+// One query per lane, each with its own window around its cell, for the point
+// ranked above it with the smallest (D2, id).  Rows and cells are clipped to the
+// best distance found so far (a cell whose nearest point is farther cannot hold
+// a better candidate), the lane's own row first.  Two kinds of stage:
+//  * a block of K >= 1 cells: the best is final when strictly closer than the
+//    block's exterior; the ring search then grows the block from K;
+//  * the ball (K = 0): the density window, clipped to the d_cut-ball as well;
+//    the best is final when D2 <= R - 1, since every point that close was seen
+//    (most dependent points lie within d_cut, the observation the paper makes
+//    after Lemma 2); the ring search then starts from nothing.
+template <int D, int MODE>
+__device__ __forceinline__ void search_lanes(Blk blk, const Plan &p, const Ws &w, int Kin) {
+  constexpr int W = (D + 1) / 2;
+  if (grid_skipped(w.hdr)) return;
+  const bool ball = Kin == 0;
+  const int K = ball ? p.K0 : Kin;
+  const int shift = MODE == kModeP16 ? 32 : kIdBits;
+  // the ball's bound, or no bound (a block is clipped by the best alone)
+  const int64_t C = ball ? p.R - 1 : INT64_MAX;
+  const int nrow = int(window_rows(p, K));
+  const uint4 *srec = w.srec;
+  uint64_t work = 0;  // the lane's candidate tests (profiling)
+  for (int64_t q = thread_index(blk); q < p.n; q += grid_threads(blk)) {
+    LaneGeom<D> geo;
+    lane_geom<D>(p, w.spts + q * D, geo);
+    const uint64_t Ki = w.sK[q];
+    uint32_t qk[W];
+    if (MODE == kModeP16) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) qk[k] = w.spk[q * W + k];
+    }
+    // p16: key (D2 << 32) | id while searching; i64: (D2 << 27) | id throughout
+    uint64_t best = kNoKey;
+    // one candidate: the rank test and the (D2, id) minimum
+    auto consider = [&](uint32_t j) {
+      uint64_t kj, key;
+      uint32_t cw[W];
+      if (MODE == kModeP16 && W <= 2 && srec) {  // words and rank key in one load
+        const uint4 rec = srec[j];
+        cw[0] = rec.x;
+        cw[W - 1] = W == 2 ? rec.y : rec.x;
+        kj = (uint64_t(rec.w) << 32) | rec.z;
+      } else {
+        kj = w.sK[j];
+        if (MODE == kModeP16) load_words<W>(w.spk + int64_t(j) * W, cw);
+      }
+      if (MODE == kModeP16) {
+        int32_t d2 = dot2_self_v(pk_sub16(qk[0], cw[0]), 0);
+#pragma unroll
+        for (int k = 1; k < W; ++k) d2 = dot2_self_v(pk_sub16(qk[k], cw[k]), d2);
+        key = (uint64_t(uint32_t(d2)) << 32) | uint32_t(~uint32_t(kj));
+      } else {
+        int64_t d2 = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const int64_t df = int64_t(geo.x[k] - w.spts[int64_t(j) * D + k]);
+          d2 += df * df;
+        }
+        key = (uint64_t(d2) << kIdBits) | uint32_t(~uint32_t(kj));
+      }
+      best = (kj > Ki && key < best) ? key : best;
+    };
+    bool done = false;
+    if constexpr (D <= 4) {
+      if (K == 1 && p.gm == D) {  // compile-time rows
+        auto visit = [&](uint32_t b, uint32_t e) {
+          work += e - b;
+          for (uint32_t j = b; j < e; ++j) consider(j);
+        };
+        if (MODE == kModeP16) {  // squared gaps of a packed-path window stay below 2^31
+          auto clip = [&]() {
+            return uint32_t(best == kNoKey ? (ball ? uint64_t(C) : uint64_t(UINT32_MAX)) : min(uint64_t(C), best >> 32));
+          };
+          walk_k1<D, uint32_t>(p, geo, w.cnt, clip, visit);
+        } else {
+          auto clip = [&]() { return best == kNoKey ? C : min(C, int64_t(best >> kIdBits)); };
+          walk_k1<D, int64_t>(p, geo, w.cnt, clip, visit);
+        }
+        done = true;
+      }
+    }
+    if (!done) {
+      RowWalk<D> rw(K, true);
+      for (int r0 = 0; r0 < nrow; r0 += kLaneRowChunk) {
+        // cell ranges of the chunk's rows first (independent loads), then their candidates
+        const int64_t clip = best == kNoKey ? C : min(C, int64_t(best >> shift));
+        uint32_t bb[kLaneRowChunk], ee[kLaneRowChunk];
+#pragma unroll
+        for (int c = 0; c < kLaneRowChunk; ++c) {
+          bb[c] = ee[c] = 0;
+          if (r0 + c < nrow) lane_row<D>(p, geo, rw, K, clip, w.cnt, &bb[c], &ee[c]);
+          rw.next(p, K);
+        }
+#pragma unroll
+        for (int c = 0; c < kLaneRowChunk; ++c) {
+          work += ee[c] - bb[c];
+          for (uint32_t j = bb[c]; j < ee[c]; ++j) consider(j);
+        }
+      }
+    }
+    if (MODE == kModeP16 && best != kNoKey) best = ((best >> 32) << kIdBits) | (best & 0xFFFFFFFFu);
+    bool resolved;
+    if (ball) {
+      resolved = best != kNoKey && int64_t(best >> kIdBits) <= C;
+    } else {
+      const uint64_t ext = lane_exterior_d2<D>(p, geo, K);
+      resolved = ext == kNoKey || (best != kNoKey && (best >> kIdBits) < ext);
+    }
+    w.best[q] = best;
+    w.flag[q] = resolved ? 0 : 1;
+  }
+  if (p.count_work) add_work(w.hdr, kWorkSearch, work);
 }
 
 // One search stage.  Each wave takes `group` consecutive tasks, gathers their
@@ -139,6 +256,7 @@ __device__ __forceinline__ void search_batch(const Plan &p, const Ws &w, int Kin
 // through an LDS queue, and searches each batch's window of radius K.
 template <int D, int MODE>
 __device__ __forceinline__ void search_body(Blk blk, const Plan &p, const Ws &w, int K, int group, int first) {
+  if (grid_skipped(w.hdr)) return;
   __shared__ uint32_t queue_all[kWavesPerBlock][2 * kWave + 1];  // + a spare slot
   uint32_t *queue = queue_all[threadIdx.x / kWave];
   const int lane = lane_id();
@@ -146,6 +264,7 @@ __device__ __forceinline__ void search_body(Blk blk, const Plan &p, const Ws &w,
   const uint32_t ntasks = uniform(as_const(&w.hdr->ntasks)[0]);
   const uint32_t ngroups = (ntasks + uint32_t(group) - 1) / uint32_t(group);
   const uint64_t below = (uint64_t(1) << lane) - 1;
+  uint64_t work = 0;  // candidate tests of valid queries (wave-uniform; profiling)
 
   const uint32_t nw = grid_waves(blk);
   for (uint32_t gi = wave_index(blk); gi < ngroups; gi += nw) {
@@ -157,7 +276,7 @@ __device__ __forceinline__ void search_body(Blk blk, const Plan &p, const Ws &w,
       const uint32_t strip = uniform(uint32_t(tc[4 * int64_t(t) + 2]));
       if (pending != 0 && strip != cur) {  // a batch never spans two strips
         const uint32_t qv = queue[min(uint32_t(lane), pending - 1)];
-        search_batch<D, MODE>(p, w, K, first != 0, cur, qv, uint32_t(lane) < pending);
+        search_batch<D, MODE>(p, w, K, first != 0, cur, qv, uint32_t(lane) < pending, &work);
         pending = 0;
       }
       cur = strip;
@@ -168,7 +287,7 @@ __device__ __forceinline__ void search_body(Blk blk, const Plan &p, const Ws &w,
       pending += uint32_t(__popcll(m));
       __builtin_amdgcn_wave_barrier();
       if (pending >= uint32_t(kWave)) {
-        search_batch<D, MODE>(p, w, K, first != 0, cur, queue[lane], true);
+        search_batch<D, MODE>(p, w, K, first != 0, cur, queue[lane], true, &work);
         const uint32_t moved = queue[kWave + lane];  // entries kWave.. move to the front
         __builtin_amdgcn_wave_barrier();
         queue[lane] = moved;
@@ -178,9 +297,10 @@ __device__ __forceinline__ void search_body(Blk blk, const Plan &p, const Ws &w,
     }
     if (pending != 0) {
       const uint32_t qv = queue[min(uint32_t(lane), pending - 1)];
-      search_batch<D, MODE>(p, w, K, first != 0, cur, qv, uint32_t(lane) < pending);
+      search_batch<D, MODE>(p, w, K, first != 0, cur, qv, uint32_t(lane) < pending, &work);
     }
   }
+  if (p.count_work) add_work(w.hdr, kWorkSearch, lane == 0 ? work : 0);
 }
 
 // Open points after the search stages, as a list in cell order.  Each thread
@@ -226,13 +346,6 @@ __device__ __forceinline__ void collect_body(Blk blk, const Plan &p, const uint8
 
 // -------------------------------------------------------------------- ring k
 
-struct SegLds {
-  uint32_t off[kWave];  // exclusive prefix of the lanes' candidate counts
-  uint32_t b1[kWave];
-  uint32_t n1[kWave];
-  uint32_t b2[kWave];
-};
-
 __device__ __forceinline__ int64_t gap_to(int32_t x, int64_t lo, int64_t hi) {
   return x < lo ? lo - x : (x > hi ? x - hi : 0);
 }
@@ -259,26 +372,38 @@ __device__ __forceinline__ uint64_t exact_d2_v(const int32_t *a, const int32_t *
   return uint64_t(s);
 }
 
-// Ring search for the points the search stages left open.  The searched block
-// grows from the cells within k0 (the last stage's radius) of the point's cell
-// to k1 = 2 k0 (an annulus per
-// pass, so a sparse neighbourhood needs a logarithmic number of passes).  In
-// every row of the annulus the cell range is clipped to the cells that can
-// still hold a point within the best distance so far, and a row farther than
-// that is skipped.  The point is final once its best candidate is strictly
-// closer than the exterior of the block; it goes to the prefix scan when the
-// passes have cost more than that scan would.
+// Ring search for the points the search stages left open, one wave per point.
+// The searched block grows from the cells within k0 (the last stage's radius)
+// of the point's cell to k1 = 2 k0 (an annulus per pass, so a sparse
+// neighbourhood needs a logarithmic number of passes).  In every row of the
+// annulus the cell range is clipped to the cells that can still hold a point
+// within the best distance so far, and a row farther than that is skipped.  A
+// pass takes its rows kRingRows per lane at a time (their cell ranges loaded
+// together), flattens their candidates over the wave and tests two per lane at a
+// time, so a wide, mostly empty annulus costs few memory round trips.  The point
+// is final once its best candidate is strictly closer than the exterior of the
+// block; it goes to the prefix scan when the passes have cost more than that
+// scan would.
+constexpr int kRingRows = 4;  // rows per lane per round
+
+struct SegLds {
+  uint32_t off[kWave];                // exclusive prefix of the lanes' candidate counts
+  uint2 seg[kWave][2 * kRingRows];    // each lane's row pieces: {first position, count}
+};
+
 template <int D>
 __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, int k_start) {
   __shared__ SegLds lds_all[kWavesPerBlock];
   SegLds &lds = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
+  if (grid_skipped(w.hdr)) return;
   const uint32_t nunres = uniform(as_const(&w.hdr->n_unres)[0]);
   DPC_CONST(int32_t) *spc = as_const(w.spts);
   DPC_CONST(uint64_t) *sKc = as_const(w.sK);
   DPC_CONST(uint32_t) *unres = as_const(w.unres);
   DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
 
+  uint64_t work = 0;  // candidate tests (wave-uniform; profiling)
   const uint32_t nw = grid_waves(blk);
   for (uint32_t u = wave_index(blk); u < nunres; u += nw) {
     const uint32_t q = uniform(unres[u]);
@@ -290,9 +415,8 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
     }
     const int32_t xs = uniform(spc[int64_t(q) * D + (p.gm - 1)]);  // coordinate along the strip dimension
     const uint64_t Ki = uniform(sKc[q]);
-    const uint32_t id = uint32_t(~uint32_t(Ki));
     const int64_t rho = int64_t(Ki >> 32);
-    uint64_t best = uniform(w.best[id]);
+    uint64_t best = uniform(w.best[q]);
     const uint32_t prefix = uniform(rstart[p.n - rho + 1]);
     const int64_t budget = min(int64_t(prefix / kWave) + 2, int64_t(p.ring_cap));
     int64_t cost = 0;
@@ -305,87 +429,131 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
       int64_t nrows = 1;
       for (int t = 0; t < p.gm - 1; ++t) nrows *= side;
       const uint64_t bestd2 = best >> kIdBits;  // huge when there is no best yet
-      for (int64_t rb = 0; rb < nrows; rb += kWave) {
-        uint32_t b1 = 0, n1 = 0, b2 = 0, n2 = 0;
-        const int64_t r0 = rb + lane;
-        if (r0 < nrows) {
-          int64_t r = r0, rowk = 0, md = 0;
-          bool ok = true, outer = false;
+      for (int64_t rb = 0; rb < nrows; rb += int64_t(kWave) * kRingRows) {
+        uint2 sg[2 * kRingRows];
+        uint32_t mine = 0;  // this lane's candidates in the round
 #pragma unroll
-          for (int t = 0; t < D - 1; ++t) {
-            if (t < p.gm - 1) {
-              const int32_t o = int32_t(r % side) - k1;
-              r /= side;
-              const int32_t nb = c[t] + o;
-              ok = ok && nb >= 0 && nb < p.nc;
-              outer = outer || o > k0 || o < -k0;
-              rowk = rowk * p.nc + nb;
-              const int64_t gp = gap_to(x[t], int64_t(nb) * p.L, int64_t(nb + 1) * p.L - 1);
-              md += gp * gp;
-            }
-          }
-          if (ok && uint64_t(md) <= bestd2) {
-            // strip-dimension cells that can hold a point within the best distance
-            const int32_t cl = xs / p.L;
-            int32_t lo = max(cl - k1, 0), hi = min(cl + k1, p.nc - 1);
-            if (bestd2 < (uint64_t(1) << 38)) {
-              const int64_t rr = isqrt_floor(bestd2 - uint64_t(md));
-              const int32_t a = int32_t(max(int64_t(xs) - rr, int64_t(0)));
-              const int32_t c2 = int32_t(min(int64_t(xs) + rr, int64_t(DPC_COORD_LIMIT - 1)));
-              lo = max(lo, a / p.L);
-              hi = min(hi, c2 / p.L);
-            }
-            const int64_t base = rowk * p.nc;
-            if (outer) {  // the whole row lies outside the block searched so far
-              if (lo <= hi) {
-                b1 = w.cnt[base + lo];
-                n1 = w.cnt[base + hi + 1] - b1;
+        for (int i = 0; i < kRingRows; ++i) {
+          sg[2 * i] = make_uint2(0u, 0u);
+          sg[2 * i + 1] = make_uint2(0u, 0u);
+          const int64_t r0 = rb + int64_t(i) * kWave + lane;
+          if (r0 < nrows) {
+            // row offsets: digits of r0 in base `side` (32-bit division while it fits)
+            int32_t off[D > 1 ? D - 1 : 1];
+            if (nrows <= int64_t(UINT32_MAX)) {
+              uint32_t r = uint32_t(r0);
+              const uint32_t us = uint32_t(side);
+#pragma unroll
+              for (int t = 0; t < D - 1; ++t) {
+                off[t] = int32_t(r % us) - k1;
+                r /= us;
               }
-            } else {  // two pieces: left and right of the searched block
-              const int32_t l_hi = min(hi, cl - k0 - 1), r_lo = max(lo, cl + k0 + 1);
-              if (lo <= l_hi) {
-                b1 = w.cnt[base + lo];
-                n1 = w.cnt[base + l_hi + 1] - b1;
+            } else {
+              int64_t r = r0;
+#pragma unroll
+              for (int t = 0; t < D - 1; ++t) {
+                off[t] = int32_t(r % side) - k1;
+                r /= side;
               }
-              if (r_lo <= hi) {
-                b2 = w.cnt[base + r_lo];
-                n2 = w.cnt[base + hi + 1] - b2;
+            }
+            int64_t md = 0;
+            int32_t rowk = 0;  // row index of the cell table (ncells < 2^31)
+            bool ok = true, outer = false;
+#pragma unroll
+            for (int t = 0; t < D - 1; ++t) {
+              if (t < p.gm - 1) {
+                const int32_t o = off[t];
+                const int32_t nb = c[t] + o;
+                ok = ok && nb >= 0 && nb < p.nc;
+                outer = outer || o > k0 || o < -k0;
+                rowk = rowk * p.nc + nb;
+                const int64_t gp = cell_gap(x[t], nb, p.L);
+                md += gp * gp;
+              }
+            }
+            if (ok && uint64_t(md) <= bestd2) {
+              // strip-dimension cells that can hold a point within the best distance
+              const int32_t cl = xs / p.L;
+              int32_t lo = max(cl - k1, 0), hi = min(cl + k1, p.nc - 1);
+              if (bestd2 < (uint64_t(1) << 38)) {
+                const int64_t rr = isqrt_floor(bestd2 - uint64_t(md));
+                const int32_t a = int32_t(max(int64_t(xs) - rr, int64_t(0)));
+                const int32_t c2 = int32_t(min(int64_t(xs) + rr, int64_t(DPC_COORD_LIMIT - 1)));
+                lo = max(lo, a / p.L);
+                hi = min(hi, c2 / p.L);
+              }
+              const int32_t base = rowk * p.nc;
+              if (outer) {  // the whole row lies outside the block searched so far
+                if (lo <= hi) {
+                  const uint32_t b = w.cnt[base + lo];
+                  sg[2 * i] = make_uint2(b, w.cnt[base + hi + 1] - b);
+                }
+              } else {  // two pieces: left and right of the searched block
+                const int32_t l_hi = min(hi, cl - k0 - 1), r_lo = max(lo, cl + k0 + 1);
+                if (lo <= l_hi) {
+                  const uint32_t b = w.cnt[base + lo];
+                  sg[2 * i] = make_uint2(b, w.cnt[base + l_hi + 1] - b);
+                }
+                if (r_lo <= hi) {
+                  const uint32_t b = w.cnt[base + r_lo];
+                  sg[2 * i + 1] = make_uint2(b, w.cnt[base + hi + 1] - b);
+                }
               }
             }
           }
         }
+#pragma unroll
+        for (int i = 0; i < 2 * kRingRows; ++i) mine += sg[i].y;
         uint32_t total;
-        const uint32_t off = wave_exclusive_scan(n1 + n2, &total);
+        const uint32_t off = wave_exclusive_scan(mine, &total);
         total = uniform(total);
-        cost += 1 + (total + kWave - 1) / kWave;
-        // Stop before a batch that would cost more than scanning the density
+        cost += kRingRows + (total + kWave - 1) / kWave;
+        // Stop before a round that would cost more than scanning the density
         // prefix (a dense neighbourhood around a density peak).
         if (cost >= budget) break;
+        work += total;
         lds.off[lane] = off;
-        lds.b1[lane] = b1;
-        lds.n1[lane] = n1;
-        lds.b2[lane] = b2;
+#pragma unroll
+        for (int i = 0; i < 2 * kRingRows; ++i) lds.seg[lane][i] = sg[i];
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         uint64_t lbest = kNoKey;
-        for (uint32_t fb = 0; fb < total; fb += kWave) {
-          const uint32_t f = fb + uint32_t(lane);
-          if (f < total) {
+        for (uint32_t fb = 0; fb < total; fb += 2 * kWave) {
+          // two candidates per lane: both positions first, then both loads
+          uint32_t pos[2];
+          bool have[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const uint32_t f = fb + uint32_t(h * kWave + lane);
+            have[h] = f < total;
             int s = 0;  // last lane whose offset is <= f
 #pragma unroll
             for (int step = 32; step > 0; step >>= 1)
               if (lds.off[s + step] <= f) s += step;
-            const uint32_t rel = f - lds.off[s];
-            const uint32_t n1s = lds.n1[s];
-            const uint32_t pos = rel < n1s ? lds.b1[s] + rel : lds.b2[s] + (rel - n1s);
-            const uint64_t kj = w.sK[pos];
-            if (kj > Ki) {
-              int32_t y[D];
+            uint32_t rel = f - lds.off[s], at = 0;
+            bool found = false;
 #pragma unroll
-              for (int t = 0; t < D; ++t) y[t] = w.spts[int64_t(pos) * D + t];
-              const uint64_t key = (exact_d2_v<D>(x, y) << kIdBits) | uint32_t(~uint32_t(kj));
-              lbest = key < lbest ? key : lbest;
+            for (int i = 0; i < 2 * kRingRows; ++i) {
+              const uint2 g = lds.seg[s][i];
+              const bool in = !found && rel < g.y;
+              at = in ? g.x + rel : at;
+              rel = (found || in) ? rel : rel - g.y;
+              found = found || in;
             }
+            pos[h] = have[h] ? at : 0u;
+          }
+          uint64_t kj[2];
+          int32_t y[2][D];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            kj[h] = w.sK[pos[h]];
+#pragma unroll
+            for (int t = 0; t < D; ++t) y[h][t] = w.spts[int64_t(pos[h]) * D + t];
+          }
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const uint64_t key = (exact_d2_v<D>(x, y[h]) << kIdBits) | uint32_t(~uint32_t(kj[h]));
+            lbest = (have[h] && kj[h] > Ki && key < lbest) ? key : lbest;
           }
         }
         __builtin_amdgcn_wave_barrier();
@@ -412,12 +580,13 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
     }
     // Every lane stores the same values (no lane-divergent branch in the loop);
     // `defer` is wave-uniform, so its branch is a scalar one.
-    w.best[id] = best;
+    w.best[q] = best;
     if (uniform(defer ? 1u : 0u) != 0u) {
       const uint32_t slot = uniform(wave_append(&w.hdr->n_peaks, lane == 0));
       w.peaks[slot] = q;
     }
   }
+  if (p.count_work) add_work(w.hdr, kWorkRing, lane == 0 ? work : 0);
 }
 
 // -------------------------------------------------------------------- peaks
@@ -445,12 +614,14 @@ template <int D>
 __device__ __forceinline__ void peaks_body(Blk blk, const Plan &p, const Ws &w) {
   constexpr int B = 16 / D > 0 ? 16 / D : 1;  // candidates per scalar-load batch
   const int lane = lane_id();
+  if (grid_skipped(w.hdr)) return;
   const uint32_t npeaks = uniform(as_const(&w.hdr->n_peaks)[0]);
   const uint32_t ngroups = (npeaks + kWave - 1) / kWave;
   const uint32_t nchunks = uint32_t((p.n + kPeakChunk - 1) / kPeakChunk);
   const uint64_t units = uint64_t(ngroups) * nchunks;
   DPC_CONST(int32_t) *rpc = as_const(w.rpts);
   DPC_CONST(int32_t) *ridc = as_const(w.rid);
+  uint64_t work = 0;  // candidate tests of owned points (wave-uniform; profiling)
 
   const uint32_t nw = grid_waves(blk);
   for (uint64_t u = wave_index(blk); u < units; u += nw) {
@@ -465,6 +636,7 @@ __device__ __forceinline__ void peaks_body(Blk blk, const Plan &p, const Ws &w) 
     const uint32_t r0 = ch * uint32_t(kPeakChunk);
     const uint32_t r1 = min(r0 + uint32_t(kPeakChunk), uint32_t(uniform(wave_max_i32(int32_t(bend)))));
     if (r0 >= r1) continue;  // wave-uniform: the chunk lies past every lane's prefix
+    work += uint64_t(r1 - r0) * min(uint32_t(kWave), npeaks - g * uint32_t(kWave));
     int32_t x[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) x[t] = w.spts[int64_t(q) * D + t];
@@ -509,16 +681,21 @@ __device__ __forceinline__ void peaks_body(Blk blk, const Plan &p, const Ws &w) 
     // address serialise in L2.  (A plain if-region: no loop depends on it.)
     const bool own = g * uint32_t(kWave) + uint32_t(lane) < npeaks;
     if (own && lbest != kNoKey)
-      atomicMin(reinterpret_cast<unsigned long long *>(&w.best[id]), static_cast<unsigned long long>(lbest));
+      atomicMin(reinterpret_cast<unsigned long long *>(&w.best[q]), static_cast<unsigned long long>(lbest));
   }
+  if (p.count_work) add_work(w.hdr, kWorkPeaks, lane_id() == 0 ? work : 0);
 }
 
 // -------------------------------------------------------------------- finish
 
-__device__ __forceinline__ void finish_body(Blk blk, const Plan &p, const uint64_t *__restrict__ best,
-                                            int32_t *__restrict__ dep, double *__restrict__ delta) {
+// The outputs in id order: each id reads its cell-order position (contiguous
+// stores, cache-friendly gathered reads); rho too when `rho` is not null.
+__device__ __forceinline__ void finish_body(Blk blk, const Plan &p, const Ws &w, int32_t *__restrict__ dep,
+                                            double *__restrict__ delta, int32_t *__restrict__ rho) {
+  if (grid_skipped(w.hdr)) return;
   for (int64_t i = thread_index(blk); i < p.n; i += grid_threads(blk)) {
-    const uint64_t key = best[i];
+    const uint32_t q = w.key[i];
+    const uint64_t key = w.best[q];
     if (key == kNoKey) {
       dep[i] = -1;
       delta[i] = __builtin_huge_val();
@@ -526,6 +703,7 @@ __device__ __forceinline__ void finish_body(Blk blk, const Plan &p, const uint64
       dep[i] = int32_t(key & kIdMask);
       delta[i] = __builtin_sqrt(double(key >> kIdBits));  // correctly rounded (IEEE sqrt)
     }
+    if (rho) rho[i] = int32_t(w.sK[q] >> 32);
   }
 }
 
@@ -534,6 +712,14 @@ __device__ __forceinline__ void finish_body(Blk blk, const Plan &p, const uint64
 template <int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_search(Plan p, Ws w, int K, int group, int first) {
   search_body<D, MODE>(grid_blk(), p, w, K, group, first);
+}
+// Stage 0 covers every point with a grid sized to them, renumbered per XCD; the
+// list stages run on a grid sized for the worst case, most of whose blocks find
+// nothing to do, so their blocks keep the dispatcher's order (renumbering would
+// put all the work on one XCD).
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_search_lanes(Plan p, Ws w, int K) {
+  search_lanes<D, MODE>(xcd_blk(), p, w, K);
 }
 __global__ __launch_bounds__(kBlock) void k_collect(Plan p, Ws w) { collect_body(grid_blk(), p, w.flag, w.unres, w.hdr); }
 template <int D>
@@ -544,8 +730,8 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_peaks(Plan p, Ws w) {
   peaks_body<D>(grid_blk(), p, w);
 }
-__global__ __launch_bounds__(kBlock) void k_finish(Plan p, Ws w, int32_t *dep, double *delta) {
-  finish_body(grid_blk(), p, w.best, dep, delta);
+__global__ __launch_bounds__(kBlock) void k_finish(Plan p, Ws w, int32_t *dep, double *delta, int32_t *rho) {
+  finish_body(grid_blk(), p, w, dep, delta, rho);
 }
 
 // Many-job forms: virtual block v of map m runs the body for its job.
@@ -566,7 +752,12 @@ __global__ __launch_bounds__(kBlock) void kb_search(const JobDev *jobs, VMap m, 
     const int K = uniform(int32_t(as_const(jobs)[j].p.stageK[st]));
     const int group = uniform(int32_t(as_const(jobs)[j].p.stageGroup[st]));
     const int mode = uniform(int32_t(as_const(jobs)[j].p.stageMode[st]));
-    if (mode == kModeP16)
+    if (p.lanes) {
+      if (mode == kModeP16)
+        search_lanes<D, kModeP16>(k, p, w, K);
+      else
+        search_lanes<D, kModeI64>(k, p, w, K);
+    } else if (mode == kModeP16)
       search_body<D, kModeP16>(k, p, w, K, group, st == 0 ? 1 : 0);
     else
       search_body<D, kModeI64>(k, p, w, K, group, st == 0 ? 1 : 0);
@@ -597,15 +788,22 @@ __global__ __launch_bounds__(kBlock) void kb_peaks(const JobDev *jobs, VMap m) {
 
 __global__ __launch_bounds__(kBlock) void kb_finish(const JobDev *jobs, VMap m) {
   DPC_FOR_VBLOCKS(m)
-  finish_body(k, p, w.best, as_const(jobs)[j].dep, as_const(jobs)[j].delta);
+  finish_body(k, p, w, as_const(jobs)[j].dep, as_const(jobs)[j].delta, as_const(jobs)[j].rho);
 }
 }
 
 #undef DPC_FOR_VBLOCKS
 
 template <int D>
-hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta, hipStream_t s) {
-  {
+hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta, int32_t *rho, hipStream_t s) {
+  if (p.lanes) {  // one stage in lane form
+    ProfScope ps(s, kProfSearch);
+    const unsigned blocks = blocks_for(p.n, kBlock);
+    if (p.stageMode[0] == kModeP16)
+      DPC_LAUNCH((k_search_lanes<D, kModeP16>), blocks, kBlock, s, p, w, p.stageK[0]);
+    else
+      DPC_LAUNCH((k_search_lanes<D, kModeI64>), blocks, kBlock, s, p, w, p.stageK[0]);
+  } else {
     ProfScope ps(s, kProfSearch);
     for (int st = 0; st < p.nstages; ++st) {
       const int K = p.stageK[st], group = p.stageGroup[st];
@@ -628,61 +826,76 @@ hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta,
     DPC_LAUNCH((k_peaks<D>), rb, kBlock, s, p, w);
   }
   ProfScope ps(s, kProfFinish);
-  DPC_LAUNCH((k_finish), blocks_for(p.n, kBlock), kBlock, s, p, w, dep, delta);
+  DPC_LAUNCH((k_finish), blocks_for(p.n, kBlock), kBlock, s, p, w, dep, delta, rho);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, hipStream_t s) {
+hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, int32_t *rho, hipStream_t s) {
   switch (p.d) {
-    case 1: return launch_dep_d<1>(p, w, dep, delta, s);
-    case 2: return launch_dep_d<2>(p, w, dep, delta, s);
-    case 3: return launch_dep_d<3>(p, w, dep, delta, s);
-    case 4: return launch_dep_d<4>(p, w, dep, delta, s);
-    case 5: return launch_dep_d<5>(p, w, dep, delta, s);
-    case 6: return launch_dep_d<6>(p, w, dep, delta, s);
-    case 7: return launch_dep_d<7>(p, w, dep, delta, s);
-    case 8: return launch_dep_d<8>(p, w, dep, delta, s);
+    case 1: return launch_dep_d<1>(p, w, dep, delta, rho, s);
+    case 2: return launch_dep_d<2>(p, w, dep, delta, rho, s);
+    case 3: return launch_dep_d<3>(p, w, dep, delta, rho, s);
+    case 4: return launch_dep_d<4>(p, w, dep, delta, rho, s);
+    case 5: return launch_dep_d<5>(p, w, dep, delta, rho, s);
+    case 6: return launch_dep_d<6>(p, w, dep, delta, rho, s);
+    case 7: return launch_dep_d<7>(p, w, dep, delta, rho, s);
+    case 8: return launch_dep_d<8>(p, w, dep, delta, rho, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-// Stages, ring search and prefix scan of every dimension group, then finish.
-// The open-point lists are collected for all jobs after the stages of every
-// group have run, so the groups' stages go first.
-hipError_t batch_dependent(const BatchMaps &B, hipStream_t s) {
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int g = 0; g < B.ngroups; ++g) {
-      VMap m = B.work;
-      m.v0 = B.gwork0[g];
-      m.v1 = B.gwork1[g];
-      if (!vgrid(m)) continue;
-      switch (B.gdim[g]) {
-#define DPC_GROUP(DD)                                                                               \
-  case DD:                                                                                          \
-    if (pass == 0) {                                                                                \
-      ProfScope ps(s, kProfSearch);                                                                 \
-      for (int st = 0; st < B.max_stages; ++st) DPC_LAUNCH((kb_search<DD>), vgrid(m), kBlock, s, B.jobs, m, st); \
-    } else {                                                                                        \
-      {                                                                                             \
-        ProfScope ps(s, kProfRingK);                                                                \
-        DPC_LAUNCH((kb_ringk<DD>), vgrid(m), kBlock, s, B.jobs, m);                                 \
-      }                                                                                             \
-      ProfScope ps(s, kProfPeaks);                                                                  \
-      DPC_LAUNCH((kb_peaks<DD>), vgrid(m), kBlock, s, B.jobs, m);                                   \
-    }                                                                                               \
-    break;
-        DPC_GROUP(1) DPC_GROUP(2) DPC_GROUP(3) DPC_GROUP(4) DPC_GROUP(5) DPC_GROUP(6) DPC_GROUP(7) DPC_GROUP(8)
-#undef DPC_GROUP
-        default: return hipErrorInvalidValue;
-      }
-    }
-    if (pass == 0 && vgrid(B.pts)) {
+// Search stages, ring search and prefix scan of every dimension group, then
+// finish.  The open points are gathered (kb_collect) after the stages of every
+// group, so the groups' stages go first.
+template <int DD>
+void batch_dep_group(const BatchMaps &B, const VMap &m, int what, int st, hipStream_t s) {
+  if (what == 0) {
+    DPC_LAUNCH((kb_search<DD>), vgrid(m), kBlock, s, B.jobs, m, st);
+  } else {
+    {
       ProfScope ps(s, kProfRingK);
-      DPC_LAUNCH((kb_collect), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+      DPC_LAUNCH((kb_ringk<DD>), vgrid(m), kBlock, s, B.jobs, m);
+    }
+    ProfScope ps(s, kProfPeaks);
+    DPC_LAUNCH((kb_peaks<DD>), vgrid(m), kBlock, s, B.jobs, m);
+  }
+}
+
+hipError_t batch_groups(const BatchMaps &B, int what, int st, hipStream_t s) {
+  for (int g = 0; g < B.ngroups; ++g) {
+    VMap m = B.work;
+    m.v0 = B.gwork0[g];
+    m.v1 = B.gwork1[g];
+    if (!vgrid(m)) continue;
+    switch (B.gdim[g]) {
+      case 1: batch_dep_group<1>(B, m, what, st, s); break;
+      case 2: batch_dep_group<2>(B, m, what, st, s); break;
+      case 3: batch_dep_group<3>(B, m, what, st, s); break;
+      case 4: batch_dep_group<4>(B, m, what, st, s); break;
+      case 5: batch_dep_group<5>(B, m, what, st, s); break;
+      case 6: batch_dep_group<6>(B, m, what, st, s); break;
+      case 7: batch_dep_group<7>(B, m, what, st, s); break;
+      case 8: batch_dep_group<8>(B, m, what, st, s); break;
+      default: return hipErrorInvalidValue;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t batch_dependent(const BatchMaps &B, hipStream_t s) {
+  hipError_t e;
+  {
+    ProfScope ps(s, kProfSearch);
+    for (int st = 0; st < B.max_stages; ++st)
+      if ((e = batch_groups(B, 0, st, s)) != hipSuccess) return e;
+  }
+  {
+    ProfScope ps(s, kProfRingK);
+    if (vgrid(B.pts)) DPC_LAUNCH((kb_collect), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  }
+  if ((e = batch_groups(B, 1, 0, s)) != hipSuccess) return e;
   ProfScope ps(s, kProfFinish);
   if (vgrid(B.pts)) DPC_LAUNCH((kb_finish), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   return hipGetLastError();

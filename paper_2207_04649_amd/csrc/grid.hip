@@ -160,13 +160,20 @@ __device__ __forceinline__ void cell_keys(Blk k, const int32_t *__restrict__ pts
   }
 }
 
-// Place every point's id at start[key] + slot: one scattered 4-byte store per
-// point.  The coordinates follow in cell order in gather_pts, so that their
-// stores are contiguous and only the reads of the (cache-resident) input scatter.
+// Place every point's id at its cell-order position start[key] + slot: one
+// scattered 4-byte store per point.  The position replaces the key (a
+// contiguous store), so the id-order outputs can later be read from cell-order
+// arrays with contiguous stores.  The coordinates follow in cell order in
+// gather_pts, so that their stores are contiguous and only the reads of the
+// (cache-resident) input scatter.
 __device__ __forceinline__ void scatter_ids(Blk k, const Plan &p, const uint32_t *__restrict__ start,
-                                            const uint32_t *__restrict__ key, const uint32_t *__restrict__ slot,
+                                            uint32_t *__restrict__ key, const uint32_t *__restrict__ slot,
                                             int32_t *__restrict__ sid) {
-  for (int64_t i = thread_index(k); i < p.n; i += grid_threads(k)) sid[int64_t(start[key[i]]) + slot[i]] = int32_t(i);
+  for (int64_t i = thread_index(k); i < p.n; i += grid_threads(k)) {
+    const uint32_t pos = start[key[i]] + slot[i];
+    sid[pos] = int32_t(i);
+    key[i] = pos;
+  }
 }
 
 __device__ __forceinline__ int32_t clamp_coord(int32_t x) {
@@ -249,17 +256,21 @@ __device__ __forceinline__ void strip_tasks(Blk k, const Plan &p, const uint32_t
 // (rho << 32) | ~id for every cell-order position, from the caller's rho.  A
 // density outside [1, n] (not produced by dpc_density) is clamped and flagged,
 // so every bucket index stays in range.
-__device__ __forceinline__ void gather_keys(Blk k, const Plan &p, const int32_t *__restrict__ rho,
-                                            const int32_t *__restrict__ sid, uint64_t *__restrict__ sK,
-                                            DevHeader *__restrict__ hdr) {
+__device__ __forceinline__ void gather_keys(Blk k, const Plan &p, const Ws &w, const int32_t *__restrict__ rho) {
+  if (grid_skipped(w.hdr)) return;
   for (int64_t q = thread_index(k); q < p.n; q += grid_threads(k)) {
-    const int32_t id = sid[q];
+    const int32_t id = w.sid[q];
     int64_t r = rho[id];
     if (r < 1 || r > p.n) {
-      atomicOr(&hdr->status, 2u);
+      atomicOr(&w.hdr->status, 2u);
       r = r < 1 ? 1 : p.n;
     }
-    sK[q] = (uint64_t(r) << 32) | uint32_t(~uint32_t(id));
+    const uint64_t key = (uint64_t(r) << 32) | uint32_t(~uint32_t(id));
+    w.sK[q] = key;
+    if (w.srec) {  // lane form, packed coordinates of d <= 4 (one or two words)
+      const uint32_t a = w.spk[q * p.words], b = p.words == 2 ? w.spk[q * p.words + 1] : 0u;
+      w.srec[q] = make_uint4(a, b, uint32_t(key), uint32_t(key >> 32));
+    }
   }
 }
 
@@ -313,23 +324,41 @@ __device__ __forceinline__ void rank_hist(Blk k, const Plan &p, const uint64_t *
   }
 }
 
-__device__ __forceinline__ void rank_scatter(Blk k, const Plan &p, const uint64_t *__restrict__ sK,
-                                             const uint32_t *__restrict__ rstart, const uint32_t *__restrict__ slot,
-                                             const int32_t *__restrict__ spts, const int32_t *__restrict__ sid,
-                                             int32_t *__restrict__ rpts, int32_t *__restrict__ rid) {
+// Rank order in two passes, like the grid: each cell-order position q stores
+// itself at its rank position (one scattered 4-byte store; the prefix-scan list
+// is free until the ring search), then every rank position copies its point
+// and id from there (contiguous stores, gathered reads).
+__device__ __forceinline__ void rank_scatter(Blk k, const Plan &p, const Ws &w) {
+  if (grid_skipped(w.hdr)) return;
   for (int64_t q = thread_index(k); q < p.n; q += grid_threads(k)) {
-    int64_t rho = int64_t(sK[q] >> 32);
+    int64_t rho = int64_t(w.sK[q] >> 32);
     rho = rho < 1 ? 1 : (rho > p.n ? p.n : rho);
-    const int64_t r = int64_t(rstart[p.n - rho]) + slot[q];
-    for (int t = 0; t < p.d; ++t) rpts[r * p.d + t] = spts[q * p.d + t];
-    rid[r] = sid[q];
+    w.peaks[int64_t(w.rcnt[p.n - rho]) + w.slot[q]] = uint32_t(q);
   }
 }
 
-// Work counters of one call; `grid` also clears the task count of the grid build.
+__device__ __forceinline__ void rank_gather(Blk k, const Plan &p, const Ws &w) {
+  if (grid_skipped(w.hdr)) return;
+  const bool v4 = p.d == 4;  // 16-byte rows (the arrays are 256-byte aligned)
+  for (int64_t r = thread_index(k); r < p.n; r += grid_threads(k)) {
+    const uint32_t q = w.peaks[r];
+    if (v4) {
+      reinterpret_cast<int4 *>(w.rpts)[r] = reinterpret_cast<const int4 *>(w.spts)[q];
+    } else {
+      for (int t = 0; t < p.d; ++t) w.rpts[r * p.d + t] = w.spts[int64_t(q) * p.d + t];
+    }
+    w.rid[r] = w.sid[q];
+  }
+}
+
+// Work counters of one call; `grid` also clears the task count of the grid build
+// and marks the grid as the call's own.
 __device__ __forceinline__ void reset_hdr(DevHeader *hdr, int grid) {
   if (threadIdx.x == 0) {
-    if (grid) hdr->ntasks = 0;
+    if (grid) {
+      hdr->ntasks = 0;
+      hdr->skip = 0;
+    }
     hdr->n_unres = 0;
     hdr->n_peaks = 0;
   }
@@ -361,16 +390,38 @@ __global__ __launch_bounds__(kBlock) void k_strip_tasks(Plan p, Ws w) {
   strip_tasks(grid_blk(), p, w.cnt, w.tcnt, w.tasks, w.hdr);
 }
 __global__ __launch_bounds__(kBlock) void k_gather_rank_keys(Plan p, const int32_t *rho, Ws w) {
-  gather_keys(grid_blk(), p, rho, w.sid, w.sK, w.hdr);
+  gather_keys(grid_blk(), p, w, rho);
 }
 __global__ __launch_bounds__(kBlock) void k_rank_hist(Plan p, Ws w) { rank_hist(grid_blk(), p, w.sK, w.rcnt, w.slot); }
-__global__ __launch_bounds__(kBlock) void k_rank_scatter(Plan p, Ws w) {
-  rank_scatter(grid_blk(), p, w.sK, w.rcnt, w.slot, w.spts, w.sid, w.rpts, w.rid);
-}
+__global__ __launch_bounds__(kBlock) void k_rank_scatter(Plan p, Ws w) { rank_scatter(grid_blk(), p, w); }
+__global__ __launch_bounds__(kBlock) void k_rank_gather(Plan p, Ws w) { rank_gather(grid_blk(), p, w); }
 __global__ void k_clear_status(DevHeader *hdr) {
   if (threadIdx.x == 0) hdr->status = 0;
 }
 __global__ void k_reset_counters(DevHeader *hdr, int grid) { reset_hdr(hdr, grid); }
+
+// A grid build starts: counters cleared, the grid marked as built for `stamp`.
+__global__ void k_stamp_grid(DevHeader *hdr, GridStamp stamp) {
+  reset_hdr(hdr, 1);
+  if (threadIdx.x < kStampWords) hdr->stamp[threadIdx.x] = stamp.w[threadIdx.x];
+  if (threadIdx.x < 4) hdr->work[threadIdx.x] = 0;
+}
+
+// A reused grid: counters cleared; the grid kernels are skipped (and the input
+// flagged as inconsistent) unless the stamp is the one this call's inputs give.
+__global__ void k_check_grid(DevHeader *hdr, GridStamp stamp) {
+  reset_hdr(hdr, 0);
+  if (threadIdx.x < 4) hdr->work[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    bool same = true;
+    for (int i = 0; i < kStampWords; ++i) same = same && hdr->stamp[i] == stamp.w[i];
+    hdr->skip = same ? 0u : 1u;
+    if (!same) {
+      hdr->ntasks = 0;
+      hdr->status |= 2u;
+    }
+  }
+}
 
 // ---- many-job kernels: virtual block v of map m runs the body for its job ----
 
@@ -478,12 +529,6 @@ __global__ __launch_bounds__(kBlock) void kb_strip_tasks(const JobDev *jobs, VMa
 }
 }
 
-__global__ __launch_bounds__(kBlock) void kb_gather_rank_keys(const JobDev *jobs, VMap m) {
-  DPC_FOR_VBLOCKS(m)
-  gather_keys(k, p, as_const(jobs)[j].rho, w.sid, w.sK, w.hdr);
-}
-}
-
 __global__ __launch_bounds__(kBlock) void kb_rank_hist(const JobDev *jobs, VMap m) {
   DPC_FOR_VBLOCKS(m)
   rank_hist(k, p, w.sK, w.rcnt, w.slot);
@@ -492,7 +537,13 @@ __global__ __launch_bounds__(kBlock) void kb_rank_hist(const JobDev *jobs, VMap 
 
 __global__ __launch_bounds__(kBlock) void kb_rank_scatter(const JobDev *jobs, VMap m) {
   DPC_FOR_VBLOCKS(m)
-  rank_scatter(k, p, w.sK, w.rcnt, w.slot, w.spts, w.sid, w.rpts, w.rid);
+  rank_scatter(k, p, w);
+}
+}
+
+__global__ __launch_bounds__(kBlock) void kb_rank_gather(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  rank_gather(k, p, w);
 }
 }
 
@@ -536,14 +587,20 @@ hipError_t reset_counters(DevHeader *hdr, bool grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, hipStream_t s) {
+hipError_t check_grid(DevHeader *hdr, const GridStamp &stamp, hipStream_t s) {
+  DPC_LAUNCH((k_check_grid), 1, kWave, s, hdr, stamp);
+  return hipGetLastError();
+}
+
+hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, const GridStamp &stamp, hipStream_t s) {
   hipError_t e;
-  if ((e = reset_counters(w.hdr, true, s)) != hipSuccess) return e;
+  DPC_LAUNCH((k_stamp_grid), 1, kWave, s, w.hdr, stamp);
   if ((e = launch_fill_u32(w.cnt, 0u, p.ncells + 1, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_cell_keys), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
   if ((e = launch_scan(w.cnt, p.ncells + 1, w.bsum, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_scatter), blocks_for(p.n, kBlock), kBlock, s, p, w);
   DPC_LAUNCH((k_gather_pts), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
+  if (p.lanes) return hipGetLastError();  // one query per lane: no strip tasks
   DPC_LAUNCH((k_strip_count), blocks_for(p.nstrips + 1, kBlock), kBlock, s, p, w);
   if ((e = launch_scan(w.tcnt, p.nstrips + 1, w.bsum, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_strip_tasks), blocks_for(p.nstrips, kBlock), kBlock, s, p, w);
@@ -561,6 +618,7 @@ hipError_t rank_sort(const Plan &p, const Ws &w, hipStream_t s) {
   DPC_LAUNCH((k_rank_hist), blocks_for(p.n, int(kRankChunk)), kBlock, s, p, w);
   if ((e = launch_scan(w.rcnt, p.n + 1, w.bsum, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_rank_scatter), blocks_for(p.n, kBlock), kBlock, s, p, w);
+  DPC_LAUNCH((k_rank_gather), blocks_for(p.n, kBlock), kBlock, s, p, w);
   return hipGetLastError();
 }
 
@@ -577,20 +635,22 @@ hipError_t batch_build_grid(const BatchMaps &B, hipStream_t s) {
   batch_scan<kArrCells>(B, B.cells, s);
   if (vgrid(B.pts)) DPC_LAUNCH((kb_scatter), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   if (vgrid(B.pts)) DPC_LAUNCH((kb_gather_pts), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  // (jobs in lane mode own no strip virtual blocks)
   if (vgrid(B.strips)) DPC_LAUNCH((kb_strip_count), vgrid(B.strips), kBlock, s, B.jobs, B.strips);
   batch_scan<kArrStrips>(B, B.strips, s);
   if (vgrid(B.strips)) DPC_LAUNCH((kb_strip_tasks), vgrid(B.strips), kBlock, s, B.jobs, B.strips);
   return hipGetLastError();
 }
 
+// (the density kernels left each job's rank keys in its workspace)
 hipError_t batch_rank(const BatchMaps &B, hipStream_t s) {
   if (vgrid(B.pts)) {
-    DPC_LAUNCH((kb_gather_rank_keys), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
     DPC_LAUNCH((kb_fill<kArrRank>), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
     DPC_LAUNCH((kb_rank_hist), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   }
   batch_scan<kArrRank>(B, B.pts, s);
   if (vgrid(B.pts)) DPC_LAUNCH((kb_rank_scatter), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  if (vgrid(B.pts)) DPC_LAUNCH((kb_rank_gather), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   return hipGetLastError();
 }
 

@@ -7,8 +7,6 @@
 // The paper propagates labels by depth-first search from the centers (Section
 // 2.2, step 4); here three rounds of in-place pointer jumping shorten the chains
 // and a final pass follows each chain to its root.
-#include <cstdlib>
-
 #include "common.h"
 
 namespace dpc {
@@ -129,12 +127,8 @@ hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const
   DPC_LAUNCH((k_zero_count), 1, kWave, s, nc);
   const unsigned blocks = blocks_for(n, kBlock);
   DPC_LAUNCH((k_label_init), blocks, kBlock, s, n, rho, dep, delta, rho_min, delta_min, label, nc, hdr);
-  int jumps = 3;
-  if (const char *env = std::getenv("DPC_LABEL_JUMPS")) {  // tuning override
-    const int v = std::atoi(env);
-    if (v >= 0 && v <= 16) jumps = v;
-  }
-  for (int k = 0; k < jumps; ++k) DPC_LAUNCH((k_jump), blocks, kBlock, s, n, label);
+  constexpr int kJumps = 3;  // then the root walk follows the (short) remaining chains
+  for (int k = 0; k < kJumps; ++k) DPC_LAUNCH((k_jump), blocks, kBlock, s, n, label);
   DPC_LAUNCH((k_root), blocks, kBlock, s, n, label);
   return hipGetLastError();
 }

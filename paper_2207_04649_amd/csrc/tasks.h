@@ -165,4 +165,256 @@ __device__ __forceinline__ void task_span(const Plan &p, TaskGeom<D> &g, int32_t
   g.x1 = g.xhi / p.L;
 }
 
+// ---------------------------------------------------------------- one query per lane
+//
+// In lane form every lane walks its own window: the rows within K of its cell
+// (the first gm - 1 cell coordinates), and in each row the strip-dimension cells
+// within K, clipped to a squared radius.  The row offsets are the same for every
+// lane (a wave-uniform walk); the cell ranges differ per lane.
+
+constexpr int kLaneRowChunk = 8;  // window rows whose cell ranges a lane loads before scanning them
+
+template <int D>
+struct LaneGeom {
+  int32_t x[D];  // the query's coordinates
+  int32_t c[D];  // its cell coordinates (first gm used)
+};
+
+template <int D>
+__device__ __forceinline__ void lane_geom(const Plan &p, const int32_t *src, LaneGeom<D> &g) {
+  if (D == 4) {
+    const int4 v = *reinterpret_cast<const int4 *>(src);  // rows of 16 bytes, 16-byte aligned
+    g.x[0] = v.x;
+    g.x[1] = v.y;
+    g.x[2 % D] = v.z;
+    g.x[3 % D] = v.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < D; ++k) g.x[k] = src[k];
+  }
+#pragma unroll
+  for (int t = 0; t < D; ++t) g.c[t] = t < p.gm ? g.x[t] / p.L : 0;
+}
+
+// Row offsets of a window of radius K, as an odometer over the first gm - 1
+// grid dimensions.  With `zigzag` each digit runs 0, -1, +1, -2, +2, ..., so the
+// query's own row comes first and nearer rows early (a search clipped to its
+// best distance then skips more rows).
+template <int D>
+struct RowWalk {
+  int32_t i[D > 1 ? D - 1 : 1];
+  bool zigzag;
+  __device__ __forceinline__ RowWalk(int K, bool zz) : zigzag(zz) {
+#pragma unroll
+    for (int t = 0; t < (D > 1 ? D - 1 : 1); ++t) i[t] = 0;
+    (void)K;
+  }
+  __device__ __forceinline__ int32_t offset(int t, int K) const {
+    if (!zigzag) return i[t] - K;
+    return (i[t] & 1) ? -((i[t] + 1) >> 1) : (i[t] >> 1);
+  }
+  __device__ __forceinline__ void next(const Plan &p, int K) {
+#pragma unroll
+    for (int t = 0; t < D - 1; ++t) {
+      if (t < p.gm - 1) {
+        if (++i[t] <= 2 * K) return;
+        i[t] = 0;
+      }
+    }
+  }
+  // `step` rows on (a carry through the digits).
+  __device__ __forceinline__ void advance(const Plan &p, int K, int step) {
+    const int side = 2 * K + 1;
+    int carry = step;
+#pragma unroll
+    for (int t = 0; t < D - 1; ++t) {
+      if (t < p.gm - 1 && carry) {
+        i[t] += carry;
+        carry = 0;
+        while (i[t] >= side) {
+          i[t] -= side;
+          ++carry;
+        }
+      }
+    }
+  }
+};
+
+// A[s] for a run-time s < D without indexing a register array by a run-time
+// value (which would move the array to memory): D selects.
+template <int D>
+__device__ __forceinline__ int32_t pick(const int32_t *a, int s) {
+  int32_t v = a[0];
+#pragma unroll
+  for (int t = 1; t < D; ++t) v = t == s ? a[t] : v;
+  return v;
+}
+
+// Gap from coordinate x to cell cc along a grid dimension (0 inside the cell).
+__device__ __forceinline__ int64_t cell_gap(int32_t x, int32_t cc, int32_t L) {
+  const int64_t lo = int64_t(cc) * L, hi = lo + L - 1;
+  return x < lo ? lo - x : (x > hi ? int64_t(x) - hi : 0);
+}
+
+// Candidate range [b, e) of the walk's current row for one lane, clipped to
+// squared radius `clip` (cells whose nearest point is farther are left out).
+// False when the row is outside the grid, beyond the radius, or empty.
+template <int D>
+__device__ __forceinline__ bool lane_row(const Plan &p, const LaneGeom<D> &g, const RowWalk<D> &rw, int K, int64_t clip,
+                                         const uint32_t *__restrict__ start, uint32_t *b, uint32_t *e) {
+  int64_t rowk = 0, dy2 = 0;
+  bool ok = true;
+#pragma unroll
+  for (int t = 0; t < D - 1; ++t) {
+    if (t < p.gm - 1) {
+      const int32_t nb = g.c[t] + rw.offset(t, K);
+      ok = ok && nb >= 0 && nb < p.nc;
+      rowk = rowk * p.nc + nb;
+      const int64_t gp = cell_gap(g.x[t], nb, p.L);
+      dy2 += gp * gp;
+    }
+  }
+  if (!ok || dy2 > clip) return false;
+  const int s = p.gm - 1;
+  const int32_t xs = pick<D>(g.x, s), cs = pick<D>(g.c, s);
+  int32_t lo = cs - K, hi = cs + K;
+  while (lo < cs) {
+    const int64_t gp = cell_gap(xs, lo, p.L);
+    if (gp * gp + dy2 <= clip) break;
+    ++lo;
+  }
+  while (hi > cs) {
+    const int64_t gp = cell_gap(xs, hi, p.L);
+    if (gp * gp + dy2 <= clip) break;
+    --hi;
+  }
+  lo = max(lo, 0);
+  hi = min(hi, p.nc - 1);
+  if (K == 1) {
+    // The four entries start[cs - 1 .. cs + 2] of the row hold both ends of any
+    // range within one cell of cs: one 16-byte load (dword-aligned loads of several
+    // dwords are allowed on this target; the table has a slack entry on each side).
+    uint4 v;
+    __builtin_memcpy(&v, start + (rowk * p.nc + cs - 1), 16);
+    const int ib = lo - (cs - 1), ie = hi + 1 - (cs - 1);  // 0..3
+    *b = ib == 0 ? v.x : (ib == 1 ? v.y : (ib == 2 ? v.z : v.w));
+    *e = ie == 0 ? v.x : (ie == 1 ? v.y : (ie == 2 ? v.z : v.w));
+  } else {
+    *b = start[rowk * p.nc + lo];
+    *e = start[rowk * p.nc + hi + 1];
+  }
+  return *b < *e;
+}
+
+constexpr int ipow3(int e) { return e <= 0 ? 1 : 3 * ipow3(e - 1); }
+
+// The radius-1 window of a lane's cell when every coordinate is indexed (gm ==
+// D), with compile-time row offsets: 3^(D-1) rows, the lane's own row first
+// (digits run 0, -1, +1), in chunks of kLaneRowChunk whose cell ranges are
+// loaded together (one 16-byte load of start[x - 1 .. x + 2] per row).  `clip()`
+// gives the squared radius, read once per chunk (a smaller one later only
+// leaves extra candidates); `visit(b, e)` scans the candidates of a row's range.
+// T holds squared gaps and radii: 32 bits when they are known to stay below
+// 2^31 (the packed path's windows), else 64.
+template <int D, class T, class ClipF, class VisitF>
+__device__ __forceinline__ void walk_k1(const Plan &p, const LaneGeom<D> &g, const uint32_t *__restrict__ start,
+                                        ClipF clip_fn, VisitF visit) {
+  constexpr int RD = D - 1;          // row dimensions
+  constexpr int NR = ipow3(RD);      // rows
+  constexpr int RA = RD > 0 ? RD : 1;
+  const int32_t L = p.L, nc = p.nc;
+  T gy[RA][3];
+  int32_t part[RA][3];
+  bool okd[RA][3];
+  int32_t stride = nc;  // the table index of row digits is sum(part) + x: row-major, x fastest
+#pragma unroll
+  for (int t = RD - 1; t >= 0; --t) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int32_t nb = g.c[t] + (i == 0 ? 0 : (i == 1 ? -1 : 1));
+      okd[t][i] = nb >= 0 && nb < nc;
+      const T gp = T(cell_gap(g.x[t], nb, L));
+      gy[t][i] = gp * gp;
+      part[t][i] = nb * stride;
+    }
+    stride *= nc;
+  }
+  const int32_t xs = g.x[D - 1], cs = g.c[D - 1];
+  const T gl = T(cell_gap(xs, cs - 1, L)), gh = T(cell_gap(xs, cs + 1, L));
+  const T gsl = gl * gl, gsh = gh * gh;
+  const bool lo_in = cs >= 1, hi_in = cs + 1 < nc;
+  const uint32_t *base = start + (cs - 1);
+#pragma unroll
+  for (int r0 = 0; r0 < NR; r0 += kLaneRowChunk) {
+    const T clip = clip_fn();
+    uint4 v[kLaneRowChunk];
+    T dy2[kLaneRowChunk];
+    bool ok[kLaneRowChunk];
+#pragma unroll
+    for (int c = 0; c < kLaneRowChunk; ++c) {
+      const int r = r0 + c;
+      if (r < NR) {
+        T dy = 0;
+        bool in = true;
+        int32_t rowk = 0;
+#pragma unroll
+        for (int t = 0; t < RD; ++t) {
+          const int i = (r / ipow3(t)) % 3;
+          dy += gy[t][i];
+          in = in && okd[t][i];
+          rowk += part[t][i];
+        }
+        dy2[c] = dy;
+        ok[c] = in && dy <= clip;
+        v[c] = make_uint4(0u, 0u, 0u, 0u);
+        if (ok[c]) __builtin_memcpy(&v[c], base + rowk, 16);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kLaneRowChunk; ++c) {
+      if (r0 + c < NR) {
+        const uint32_t b = (lo_in && gsl + dy2[c] <= clip) ? v[c].x : v[c].y;
+        const uint32_t e = (hi_in && gsh + dy2[c] <= clip) ? v[c].w : v[c].z;
+        if (ok[c] && b < e) visit(b, e);
+      }
+    }
+  }
+}
+
+// Squared distance from x to the outside of the block of cells within K of its
+// own cell (UINT64_MAX when the block covers the grid): every point outside has
+// D2 >= this, since its gap in one grid dimension alone is that large.
+template <int D>
+__device__ __forceinline__ uint64_t lane_exterior_d2(const Plan &p, const LaneGeom<D> &g, int K) {
+  int64_t gap = INT64_MAX;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    if (t < p.gm) {
+      if (g.c[t] - K >= 1) gap = min(gap, int64_t(g.x[t]) - int64_t(g.c[t] - K) * p.L + 1);
+      if (g.c[t] + K <= p.nc - 2) gap = min(gap, int64_t(g.c[t] + K + 1) * p.L - int64_t(g.x[t]));
+    }
+  }
+  return gap == INT64_MAX ? ~uint64_t(0) : uint64_t(gap) * uint64_t(gap);
+}
+
+// W consecutive 32-bit words (one vector load when aligned: W = 2 or 4 words of
+// an array with W-word elements from a 256-byte aligned base).
+template <int W>
+__device__ __forceinline__ void load_words(const uint32_t *src, uint32_t *c) {
+  if (W == 2) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(src);
+    c[0] = v.x;
+    c[1 % W] = v.y;
+  } else if (W == 4) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(src);
+    c[0] = v.x;
+    c[1 % W] = v.y;
+    c[2 % W] = v.z;
+    c[3 % W] = v.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) c[k] = src[k];
+  }
+}
+
 }  // namespace dpc

@@ -7,14 +7,16 @@ thresholds on the decision graph once rho and delta are known (Section 2.1), so
 a resident job keeps its coordinates, rho, dep and delta in HBM and a
 re-threshold reruns only the labelling (dpc_label, Defs. 4-6).
 
-Scheduling.  Work runs in slots, one HIP stream each (default priority).  The
-loop admits arrived requests in arrival order whenever a slot is free and the
-job fits the HBM budget.  Small new jobs that are waiting together share one
-slot as a many-job batch (dpc_batch_run); a large one takes a slot alone
-(dpc_run).  Idle resident jobs are evicted, least recently used first, when a
-new job needs their memory.  Requests that arrive while others are on the GPU
-are admitted as soon as a slot and memory free up, so their work overlaps on
-the device.  Latency is arrival -> labels in pinned host memory.
+Scheduling.  Work runs in slots, one HIP stream each (default priority).  New
+jobs and re-thresholds wait in two queues with slots of their own, so an O(n)
+relabel never waits behind a new job's clustering: the loop admits arrived
+requests of each queue in arrival order whenever one of its slots is free (and,
+for a new job, when it fits the HBM budget).  Small new jobs that are waiting
+together share one slot as a many-job batch (dpc_batch_run); a large one takes
+a slot alone (dpc_run).  Idle resident jobs are evicted, least recently used
+first, when a new job needs their memory.  Requests that arrive while others
+are on the GPU are admitted as soon as a slot and memory free up, so their work
+overlaps on the device.  Latency is arrival -> labels in pinned host memory.
 
 Every result equals that of the job run alone: the kernels are deterministic
 and jobs share no device memory.
@@ -43,6 +45,7 @@ class Req:
     d_cut: float = 0.0
     rho_min: int = 0
     delta_min: float = 0.0
+    seed: int = -1              # new job: the seed of its generator spec
     pick: float = 0.0           # re-threshold: picks a ready resident job at admission
     delta_factor: float = 0.0   # re-threshold: delta_min = delta_factor * the job's d_cut
     job_key: int = -1           # the job the request created or re-thresholded
@@ -50,6 +53,9 @@ class Req:
     dropped: bool = False       # re-threshold with no job ready (nothing to re-threshold)
     labels: torch.Tensor | None = None    # pinned host copies
     ncenters: torch.Tensor | None = None
+    rho: torch.Tensor | None = None       # new jobs, with keep_outputs: pinned host copies
+    dep: torch.Tensor | None = None
+    delta: torch.Tensor | None = None
 
 
 @dataclasses.dataclass(eq=False)
@@ -83,21 +89,29 @@ class Inflight:
 
 
 class Server:
+    """``slots`` streams for new jobs, ``relabel_slots`` for re-thresholds (0: they
+    share the new-job slots and queue, one FIFO for both).  With ``keep_outputs``
+    a new job's rho, dep and delta are copied to pinned host memory as well."""
+
     def __init__(self, budget_bytes: int = 64 << 30, slots: int = 4, device: str = "cuda:0",
-                 group_small: bool = True):
+                 group_small: bool = True, relabel_slots: int = 1, keep_outputs: bool = False):
         self.dev = torch.device(device)
         self.budget = int(budget_bytes)
         self.used = 0
         self.group_small = group_small
-        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
-        self.free_slots = list(range(slots))
+        self.keep_outputs = keep_outputs
+        self.shared = relabel_slots <= 0
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots + max(0, relabel_slots))]
+        self.free_slots = list(range(slots))                           # new jobs (and shared relabels)
+        self.free_relabel = list(range(slots, slots + max(0, relabel_slots)))
         self.inflight: list[Inflight] = []
         self.resident: "collections.OrderedDict[int, Resident]" = collections.OrderedDict()
         self.next_key = 0
         self.label_ws = [torch.empty(dpc.DPC_LABEL_WS_BYTES, dtype=torch.uint8, device=self.dev)
-                         for _ in range(slots)]
+                         for _ in range(len(self.streams))]
         self.stats = collections.Counter()
         self.peak_used = 0
+        self.new_outstanding = 0  # new-job requests of the run not yet admitted
 
     # ---- memory ledger ----
     @staticmethod
@@ -151,6 +165,13 @@ class Server:
                 q.ncenters = torch.empty(1, dtype=torch.int64, pin_memory=True)
                 q.labels.copy_(r.label, non_blocking=True)
                 q.ncenters.copy_(r.ncenters, non_blocking=True)
+                if self.keep_outputs:
+                    q.rho = torch.empty(r.n, dtype=torch.int32, pin_memory=True)
+                    q.dep = torch.empty(r.n, dtype=torch.int32, pin_memory=True)
+                    q.delta = torch.empty(r.n, dtype=torch.float64, pin_memory=True)
+                    q.rho.copy_(r.rho, non_blocking=True)
+                    q.dep.copy_(r.dep, non_blocking=True)
+                    q.delta.copy_(r.delta, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
         for r in jobs:
@@ -193,7 +214,7 @@ class Server:
             self.used -= f.ws_bytes
             if f.batch is not None:
                 dpc.dpc_batch_free(f.batch)
-            self.free_slots.append(f.slot)
+            (self.free_slots if f.new or self.shared else self.free_relabel).append(f.slot)
             done += len(f.reqs)
         self.inflight = keep
         return done
@@ -215,8 +236,8 @@ class Server:
         if q.kind == "rethreshold":
             ready = [k for k, r in self.resident.items() if r.ready]
             if not ready:
-                if any(not r.ready for r in self.resident.values()):
-                    return False  # a job is being computed: wait for it
+                if self.new_outstanding or any(not r.ready for r in self.resident.values()):
+                    return False  # a job is being computed or will be: wait for it
                 queue.popleft()
                 q.dropped = True
                 q.t_done = now
@@ -226,7 +247,7 @@ class Server:
             q.job_key = r.key
             q.delta_min = q.delta_factor * r.d_cut
             queue.popleft()
-            self._launch_relabel(q, r, self.free_slots.pop(0), now)
+            self._launch_relabel(q, r, (self.free_slots if self.shared else self.free_relabel).pop(0), now)
             return True
         group = [q]
         if self.group_small and q.pts.shape[0] <= SMALL_JOB:
@@ -247,6 +268,7 @@ class Server:
             queue.remove(g)
             g.job_key = self.next_key
             self.next_key += 1
+        self.new_outstanding -= len(group)
         self.used += need
         self.peak_used = max(self.peak_used, self.used)
         self._launch_new(group, self.free_slots.pop(0), now, ws_bytes)
@@ -255,23 +277,28 @@ class Server:
     def run(self, requests: list[Req], clock=time.perf_counter) -> list[Req]:
         """Replay `requests` in real time (by t_arrival); returns them with t_done set."""
         pending = collections.deque(sorted(requests, key=lambda q: q.t_arrival))
-        queue: "collections.deque[Req]" = collections.deque()
+        queues = {"new": collections.deque(), "rethreshold": collections.deque()}
+        self.new_outstanding = sum(1 for q in requests if q.kind == "new")
         finished = 0
         t0 = clock()
         while finished < len(requests):
             now = clock() - t0
             while pending and pending[0].t_arrival <= now:
-                queue.append(pending.popleft())
+                q = pending.popleft()
+                queues["new" if self.shared else q.kind].append(q)
             finished += self._retire(now)
             progressed = False
-            while queue and self.free_slots:
-                dropped = self.stats["dropped"]
-                if not self._admit(queue, now):
-                    if not self.inflight and queue[0].kind == "new":
-                        raise RuntimeError("a job does not fit the HBM budget even with nothing resident")
-                    break
-                progressed = True
-                finished += self.stats["dropped"] - dropped
+            for kind in ("rethreshold", "new"):
+                queue = queues[kind]
+                free = self.free_relabel if (kind == "rethreshold" and not self.shared) else self.free_slots
+                while queue and free:
+                    dropped = self.stats["dropped"]
+                    if not self._admit(queue, now):
+                        if not self.inflight and queue[0].kind == "new":
+                            raise RuntimeError("a job does not fit the HBM budget even with nothing resident")
+                        break
+                    progressed = True
+                    finished += self.stats["dropped"] - dropped
             if not progressed:
                 time.sleep(0.0002)
         torch.cuda.synchronize()
@@ -296,7 +323,7 @@ def trace_requests(trace, make_job) -> list[Req]:
         if r.kind == "new":
             job = make_job(r.spec)
             reqs.append(Req(k, r.t, "new", pts=job.pts, d_cut=job.d_cut, rho_min=job.rho_min,
-                            delta_min=job.delta_min))
+                            delta_min=job.delta_min, seed=r.spec.seed))
         else:
             reqs.append(Req(k, r.t, "rethreshold", rho_min=r.rho_min, pick=r.pick, delta_factor=r.delta_factor))
     return reqs

@@ -6,9 +6,12 @@
 //
 // With --batch the input holds int32 njobs and then njobs such records; all
 // jobs run through dpc_batch_run and the output holds one record per job
-// (the status fields are those of the batch calls).
+// (the status fields are those of the batch calls).  --tuning SPEC (batch only)
+// gives every job the plan options of SPEC, "key=value" items separated by ';':
+// subdiv, strip, ring, gm, lanes, and stages=K:group,K:group,...
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -46,7 +49,45 @@ void write_rec(FILE *out, int32_t st, int32_t st2, const Rec &r) {
   std::fwrite(r.label.data(), 4, r.n, out);
 }
 
-int run_batch(const char *inp, const char *outp) {
+// Plan options from a --tuning SPEC (see above); false on a malformed spec.
+bool parse_tuning(const std::string &spec, dpc_tuning *t) {
+  std::memset(t, 0, sizeof(*t));
+  size_t at = 0;
+  while (at < spec.size()) {
+    size_t end = spec.find(';', at);
+    if (end == std::string::npos) end = spec.size();
+    const std::string item = spec.substr(at, end - at);
+    at = end + 1;
+    const size_t eq = item.find('=');
+    if (eq == std::string::npos) return false;
+    const std::string k = item.substr(0, eq), v = item.substr(eq + 1);
+    if (k == "stages") {
+      int n = 0;
+      for (size_t c = 0; c < v.size() && n < 4;) {
+        int K = 0, g = 1;
+        if (std::sscanf(v.c_str() + c, "%d:%d", &K, &g) < 1) return false;
+        t->stage_radius[n] = K;
+        t->stage_group[n] = g;
+        ++n;
+        const size_t comma = v.find(',', c);
+        if (comma == std::string::npos) break;
+        c = comma + 1;
+      }
+      t->nstages = n;
+      continue;
+    }
+    const int x = std::atoi(v.c_str());
+    if (k == "subdiv") t->subdiv = x;
+    else if (k == "strip") t->strip_cells = x;
+    else if (k == "ring") t->ring_cap = x;
+    else if (k == "gm") t->grid_dims = x;
+    else if (k == "lanes") t->lanes = x;
+    else return false;
+  }
+  return true;
+}
+
+int run_batch(const char *inp, const char *outp, const dpc_tuning *tuning) {
   FILE *in = std::fopen(inp, "rb");
   if (!in) return 2;
   int32_t njobs = 0;
@@ -63,7 +104,10 @@ int run_batch(const char *inp, const char *outp) {
   }
   dpc_batch *b = nullptr;
   size_t wsb = 0;
-  int32_t st = dpc_batch_plan(jobs.data(), njobs, nullptr, &b, &wsb);
+  std::vector<dpc_tuning> tun(njobs);
+  if (tuning)
+    for (auto &t : tun) t = *tuning;
+  int32_t st = dpc_batch_plan(jobs.data(), njobs, tuning ? tun.data() : nullptr, &b, &wsb);
   int32_t st2 = st;
   if (st == DPC_OK) {
     void *ws = std::aligned_alloc(256, (wsb + 255) / 256 * 256);
@@ -81,7 +125,15 @@ int run_batch(const char *inp, const char *outp) {
 }
 
 int main(int argc, char **argv) {
-  if (argc == 4 && std::string(argv[1]) == "--batch") return run_batch(argv[2], argv[3]);
+  if (argc == 4 && std::string(argv[1]) == "--batch") return run_batch(argv[2], argv[3], nullptr);
+  if (argc == 6 && std::string(argv[1]) == "--batch" && std::string(argv[2]) == "--tuning") {
+    dpc_tuning t;
+    if (!parse_tuning(argv[3], &t)) {
+      std::fprintf(stderr, "bad --tuning spec\n");
+      return 2;
+    }
+    return run_batch(argv[4], argv[5], &t);
+  }
   if (argc != 3) {
     std::fprintf(stderr, "usage: %s [--batch] input output\n", argv[0]);
     return 2;

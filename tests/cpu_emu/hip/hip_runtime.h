@@ -37,7 +37,14 @@ enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMe
 struct uint4 {
   unsigned x, y, z, w;
 };
+struct alignas(16) int4 {
+  int x, y, z, w;
+};
+struct alignas(8) uint2 {
+  unsigned x, y;
+};
 inline uint4 make_uint4(unsigned x, unsigned y, unsigned z, unsigned w) { return uint4{x, y, z, w}; }
+inline uint2 make_uint2(unsigned x, unsigned y) { return uint2{x, y}; }
 
 template <class T>
 inline T min(T a, T b) {

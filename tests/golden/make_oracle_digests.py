@@ -14,7 +14,9 @@ Workloads (each entry is rewritten when its run ends):
 
 * blobs_20k_d2, blobs_1m_d2, walks_4m_d4: the single-job workloads;
 * batch4096: every job of the 4096-job batch workload (job k drawn from seed
-  4,000,000 + k), one record per job.
+  4,000,000 + k), one record per job;
+* serve_test: every new job of the served-workload trace the serving test
+  replays (inputs.serve_trace with n up to 200,000, see SERVE_TEST), by seed.
 
 Times: about 10 minutes for blobs_1m_d2 and 15 for batch4096 on 8 cores; the
 4M-point 4-D workload takes hours (1.6e13 + 8e12 distance evaluations).
@@ -38,6 +40,9 @@ from paper_2207_04649_amd import inputs  # noqa: E402
 from tests import digests  # noqa: E402
 
 SINGLE = ("blobs_20k_d2", "blobs_1m_d2", "walks_4m_d4")
+# the trace of the serving test: Poisson arrivals at 200 jobs/s for one second,
+# new jobs with n log-uniform in [1000, 200000], d in 2..8
+SERVE_TEST = {"rate": 200.0, "duration": 1.0, "seed": 5, "n_hi": 200_000}
 
 
 def log(msg: str) -> None:
@@ -90,9 +95,25 @@ def run_batch(count: int, workers: int) -> dict:
     return {"count": count, "jobs": recs, "oracle_seconds": round(secs, 1), "oracle_threads": scan.threads()}
 
 
+def run_serve_test(workers: int) -> dict:
+    trace = inputs.serve_trace(**SERVE_TEST)
+    specs = [r.spec for r in trace if r.kind == "new"]
+    log(f"serve_test: {len(trace)} requests, {len(specs)} new jobs, {sum(s.n for s in specs)} points")
+    recs = {}
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(workers) as ex:
+        for spec, job in zip(specs, ex.map(_make, specs, chunksize=2)):
+            out = oracle_outputs(job)
+            rec = digests.output_digests(out, short=16)
+            rec.update({"n": job.n, "d": job.d, "input": digests.input_digest(job)[:16]})
+            recs[str(spec.seed)] = rec
+    secs = time.perf_counter() - t0
+    return {"trace": SERVE_TEST, "jobs": recs, "oracle_seconds": round(secs, 1), "oracle_threads": scan.threads()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("workloads", nargs="+", help=f"any of {SINGLE} and batch4096")
+    ap.add_argument("workloads", nargs="+", help=f"any of {SINGLE}, batch4096 and serve_test")
     ap.add_argument("--workers", type=int, default=4, help="processes drawing the batch jobs")
     ap.add_argument("--save-dir", default=None, help="also keep the oracle's arrays here (.npz)")
     args = ap.parse_args()
@@ -102,6 +123,8 @@ def main() -> int:
             rec = run_single(name, args.save_dir)
         elif name.startswith("batch"):
             rec = run_batch(int(name[len("batch"):]), args.workers)
+        elif name == "serve_test":
+            rec = run_serve_test(args.workers)
         else:
             raise SystemExit(f"unknown workload {name}")
         data = digests.load()

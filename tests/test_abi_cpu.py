@@ -60,10 +60,13 @@ def test_plan_invariants(n, d, d_cut):
     assert p["cells_per_dim"] * L >= dpc.COORD_LIMIT
     gm = p["grid_dims"]
     assert 1 <= gm <= d
-    assert p["cells"] == p["cells_per_dim"] ** gm <= min(1 << 26, max(4096, 8 * n))
+    per_point = 16 if p["lanes"] else 8  # lane form: cut-off-wide cells, a larger table
+    assert p["cells"] == p["cells_per_dim"] ** gm <= min(1 << 26, max(4096, per_point * n))
+    if p["lanes"]:
+        assert p["strips"] == 0 and p["max_tasks"] == 0
     if p["mode"] == 0:  # packed 16-bit path: every coordinate indexed, |dx| < 2^15 and D2 < 2^31
         assert gm == d
-        E = (p["strip_cells"] + 2 * K0) * L
+        E = ((1 if p["lanes"] else p["strip_cells"]) + 2 * K0) * L  # a lane's window, or a strip's
         assert E - 1 <= 32767 and d * (E - 1) ** 2 <= 2 ** 31 - 1
     assert p["stages"] >= 1
     assert p["workspace_bytes"] == dpc.dpc_workspace_bytes(n, d, d_cut) > 0

@@ -130,7 +130,7 @@ def test_batch_rerun_and_tunings_agree(dpc):
     tun = [dpc.Tuning.make(subdiv=1 + k % 4, strip_cells=(0, 3, 16)[k % 3],
                            stages=[((1, 1), (3, 4)), ((2, 1),), ((1, 1), (2, 2), (4, 8)), ((0, 1),),
                                    ((0, 1), (2, 4))][k % 5],
-                           ring_cap=(0, 4, 300)[k % 3], grid_dims=(0, 2, 3, 8)[k % 4], row_split=(0, 2, 9)[k % 3])
+                           ring_cap=(0, 4, 300)[k % 3], grid_dims=(0, 2, 3, 8)[k % 4], lanes=(0, 1, 2)[k % 3])
            for k in range(len(jobs))]
     b2, _, tuned = run_batch(dpc, jobs, tun)
     for k in range(len(jobs)):
@@ -153,3 +153,40 @@ def test_batch_device_errors_name_the_job(dpc):
     pins.assert_same(to_host(b.out[1]), clamped, keys=KEYS, ctx="clamped job")
     pins.assert_same(to_host(b.out[0]), pins.run(scan, good, 300.0, 1, 900.0), keys=KEYS, ctx="good job")
     b.close()
+
+
+def _make_job(spec):
+    return spec.make()
+
+
+def test_batch4096_whole_vs_oracle_digests(dpc):
+    """All 4096 jobs of the batch workload in one batch, every job's rho, dep,
+    delta and labels against the digests of the oracle's outputs (written by an
+    oracle-only script, tests/golden/make_oracle_digests.py)."""
+    import multiprocessing as mp
+    import concurrent.futures as cf
+
+    from tests import digests
+
+    rec = digests.load().get("batch4096")
+    if rec is None:
+        pytest.skip("no oracle digests stored for the 4096-job batch")
+    specs = inputs.batch_specs(rec["count"])
+    _say(f"drawing {len(specs)} batch jobs")
+    with cf.ProcessPoolExecutor(16, mp_context=mp.get_context("spawn")) as ex:
+        made = list(ex.map(_make_job, specs, chunksize=16))
+    jobs = [(j.pts, j.d_cut, j.rho_min, j.delta_min) for j in made]
+    _say(f"batch of {len(jobs)} jobs, {sum(j[0].shape[0] for j in jobs)} points")
+    b, _, outs = run_batch(dpc, jobs)
+    bad = []
+    for k, (job, got, want) in enumerate(zip(made, outs, rec["jobs"])):
+        assert want["seed"] == specs[k].seed and want["input"] == digests.input_digest(job)[:16]
+        dg = digests.output_digests(got, short=16)
+        if any(dg[f] != want[f] for f in (*digests.OUT_KEYS, "ncenters")):
+            bad.append(k)
+    b.close()
+    if bad:
+        k = bad[0]
+        _say(f"{len(bad)} jobs differ from the oracle digests; localising job {k}")
+        pins.assert_same(outs[k], pins.run(scan, *jobs[k]), keys=KEYS, ctx=f"job {k}")
+    assert not bad, f"{len(bad)} of {len(jobs)} jobs differ from the oracle (first {bad[:10]})"

@@ -56,10 +56,11 @@ def run_emu(exe, pts, d_cut, rho_min, delta_min, extra_env=None):
     return _parse(b, 0, int(np.asarray(pts).shape[0]))[0]
 
 
-def run_emu_batch(exe, jobs):
-    """jobs: list of (pts, d_cut, rho_min, delta_min), run through the batch entry points."""
+def run_emu_batch(exe, jobs, tuning=None):
+    """jobs: list of (pts, d_cut, rho_min, delta_min), run through the batch entry points
+    (every job with the plan options of the driver's --tuning spec, if given)."""
     payload = struct.pack("<i", len(jobs)) + b"".join(_record(*j) for j in jobs)
-    b = _run(exe, ["--batch"], payload)
+    b = _run(exe, ["--batch"] + (["--tuning", tuning] if tuning else []), payload)
     outs, o = [], 0
     for j in jobs:
         out, o = _parse(b, o, int(np.asarray(j[0]).shape[0]))
@@ -120,17 +121,23 @@ def test_emulated_batch_matches_oracle(emu_exe):
         pins.assert_same(got, pins.run(scan, *job), keys=("rho", "dep", "delta", "label", "ncenters"), ctx=f"job {k}")
 
 
-@pytest.mark.parametrize("env", [
-    {"DPC_STAGES": "0:1"},                                  # ball stage, ring search from nothing
-    {"DPC_STAGES": "0:1,2:4", "DPC_GRID_DIMS": "2"},       # ball then a gathered stage, partial grid
-    {"DPC_STAGES": "1:1,3:4", "DPC_ROW_SPLIT": "3", "DPC_SUBDIV": "3"},
+@pytest.mark.parametrize("tuning", [
+    "stages=0:1",                      # ball stage, ring search from nothing
+    "stages=0:1,2:4;gm=2",             # ball then a gathered stage, partial grid
+    "stages=1:1,3:4;subdiv=3",
+    "lanes=2",                         # one query per lane, every dimension
+    "lanes=2;stages=2:1;gm=2",         # lane form, radius-2 stage, partial grid
+    "lanes=2;subdiv=2;ring=3",
+    "lanes=1",                         # tasks of 64 queries, every dimension
 ])
-def test_emulated_plan_options_match_oracle(emu_exe, env):
-    for k, (n, d, dc) in enumerate([(300, 2, 4000.0), (200, 4, 12000.0)]):
+def test_emulated_plan_options_match_oracle(emu_exe, tuning):
+    jobs = []
+    for k, (n, d, dc) in enumerate([(300, 2, 4000.0), (200, 4, 12000.0), (150, 3, 9000.0), (60, 6, 25000.0)]):
         pts = inputs.uniform_points(n, d, 131071, 500 + k)
         pts[n // 2:] = pts[: n - n // 2] + (pts[: n - n // 2] % 5)
-        pts = np.clip(pts, 0, 131071).astype(np.int32)
-        got = run_emu(emu_exe, pts, dc, 2, dc * 1.5, extra_env=env)
-        assert got["status"] == 0 and got["sync"] == 0
-        pins.assert_same(got, pins.run(scan, pts, dc, 2, dc * 1.5), keys=("rho", "dep", "delta", "label", "ncenters"),
-                         ctx=f"{env} n={n} d={d}")
+        jobs.append((np.clip(pts, 0, 131071).astype(np.int32), dc, 2, dc * 1.5))
+    outs = run_emu_batch(emu_exe, jobs, tuning)
+    for k, (job, got) in enumerate(zip(jobs, outs)):
+        assert got["status"] == 0 and got["sync"] == 0, (tuning, k)
+        pins.assert_same(got, pins.run(scan, *job), keys=("rho", "dep", "delta", "label", "ncenters"),
+                         ctx=f"{tuning} job {k}")

@@ -13,6 +13,7 @@ import pytest
 
 from oracle import dpc_oracle, scan
 from paper_2207_04649_amd import inputs
+from tests import digests
 from tests import oracle_pins as pins
 
 torch = pytest.importorskip("torch")
@@ -143,9 +144,10 @@ def test_lattice_ties(dpc):
         compare(run_gpu(dpc, pts, dc, 1, dc * 2), oracle_run(pts, dc, 1, dc * 2), ctx=f"lattice d={d}")
 
 
-def test_separate_calls_and_no_reuse(dpc):
-    job = inputs.blob_job(77, 5000, 3, 7, 500.0, 2000.0, 0.1)
-    _say("separate calls")
+@pytest.mark.parametrize("d", [3, 4])
+def test_separate_calls_and_no_reuse(dpc, d):
+    job = inputs.blob_job(77, 5000, d, 7, 500.0, 2000.0, 0.1)
+    _say(f"separate calls d={d}")
     want = oracle_run(job.pts, job.d_cut, job.rho_min, job.delta_min)
     compare(run_gpu(dpc, job.pts, job.d_cut, job.rho_min, job.delta_min, separate=True), want, "reuse")
     compare(run_gpu(dpc, job.pts, job.d_cut, job.rho_min, job.delta_min, separate=True, reuse=False), want,
@@ -204,27 +206,20 @@ def test_blobs_20k_full(dpc):
             oracle_run(job.pts, job.d_cut, job.rho_min, job.delta_min), ctx="blobs_20k")
 
 
-def check_full_size(dpc, job, n_rho=1500, n_dep=160, seed=0):
-    """Full-size run checked on samples the oracle computes one by one, and on
-    properties that hold at any size."""
-    out = run_gpu(dpc, job.pts, job.d_cut, job.rho_min, job.delta_min)
-    rng = np.random.default_rng(seed)
-    n = job.n
-    which = np.sort(rng.choice(n, size=min(n, n_rho), replace=False))
-    _say(f"{job.name}: oracle densities of {which.size} samples")
-    assert np.array_equal(out["rho"][which], scan.local_density_of(job.pts, job.d_cut, which))
-    # the densest points and the points without a dependent are checked too
-    top = np.argsort(-out["rho"], kind="stable")[:8]
-    which = np.unique(np.concatenate([rng.choice(n, size=min(n, n_dep), replace=False), top]))
-    _say(f"{job.name}: oracle dependents of {which.size} samples")
-    rho_s, dep_s, d2_s = scan.dependent_of(job.pts, job.d_cut, which, max_walk=400)
-    ok = dep_s != -2
-    assert ok.sum() >= 0.8 * which.size
-    assert np.array_equal(out["rho"][which], rho_s)
-    assert np.array_equal(out["dep"][which][ok], dep_s[ok])
-    assert np.array_equal(out["delta"][which][ok], scan.dependent_distance(d2_s[ok]))
-    # properties at any size
+def sum_rho_by_pair_count(job):
+    """n + 2 * #{i < j : D2 < R}, counted by scipy's kd-tree (closed ball of radius
+    sqrt(R - 1/2) holds exactly the integer D2 <= R - 1), independent of both paths."""
+    from scipy.spatial import cKDTree
+    R = dpc_oracle.cutoff_square(job.d_cut)
+    tree = cKDTree(job.pts.astype(np.float64))
+    return int(tree.count_neighbors(tree, math.sqrt(R - 0.5)))
+
+
+def check_properties(job, out):
+    """Properties that hold at any size (Defs. 1-6)."""
     rho, dep, delta, lab = out["rho"], out["dep"], out["delta"], out["label"]
+    _say(f"{job.name}: sum of rho against the kd-tree pair count")
+    assert int(rho.sum(dtype=np.int64)) == sum_rho_by_pair_count(job)
     assert np.count_nonzero(dep < 0) == 1
     i = np.nonzero(dep >= 0)[0]
     j = dep[i]
@@ -243,12 +238,112 @@ def check_full_size(dpc, job, n_rho=1500, n_dep=160, seed=0):
     assert out["ncenters"] == int(center.sum())
     lab_o, nc_o = scan.labels(rho, dep, delta, job.rho_min, job.delta_min)
     assert np.array_equal(lab, lab_o) and nc_o == out["ncenters"]
+
+
+def check_sampled(job, out, n_rho, n_dep, seed=0):
+    """Sampled points against the oracle computed one by one (localises a mismatch)."""
+    rng = np.random.default_rng(seed)
+    n = job.n
+    which = np.sort(rng.choice(n, size=min(n, n_rho), replace=False))
+    _say(f"{job.name}: oracle densities of {which.size} samples")
+    assert np.array_equal(out["rho"][which], scan.local_density_of(job.pts, job.d_cut, which))
+    # the densest points and the points without a dependent are checked too
+    top = np.argsort(-out["rho"], kind="stable")[:8]
+    which = np.unique(np.concatenate([rng.choice(n, size=min(n, n_dep), replace=False), top]))
+    _say(f"{job.name}: oracle dependents of {which.size} samples")
+    rho_s, dep_s, d2_s = scan.dependent_of(job.pts, job.d_cut, which, max_walk=400)
+    ok = dep_s != -2
+    assert np.array_equal(out["rho"][which], rho_s)
+    assert np.array_equal(out["dep"][which][ok], dep_s[ok])
+    assert np.array_equal(out["delta"][which][ok], scan.dependent_distance(d2_s[ok]))
+
+
+def check_full_size(dpc, job, n_rho=1500, n_dep=160, seed=0):
+    """Whole-output parity at full size: the outputs' digests against those of the
+    oracle (tests/golden/oracle_digests.json, written by an oracle-only script),
+    plus properties at any size.  On a digest mismatch, or without a digest, the
+    sampled oracle check runs to localise the difference."""
+    out = run_gpu(dpc, job.pts, job.d_cut, job.rho_min, job.delta_min)
+    rec = digests.load().get(job.name)
+    check_properties(job, out)
+    if rec is None:
+        _say(f"{job.name}: no oracle digest stored; sampled check only")
+        check_sampled(job, out, n_rho, n_dep, seed)
+        return out
+    assert rec["input"] == digests.input_digest(job), "the stored digest belongs to other inputs"
+    got = digests.output_digests(out)
+    bad = [k for k in digests.OUT_KEYS if got[k] != rec[k]]
+    if got["ncenters"] != rec["ncenters"]:
+        bad.append("ncenters")
+    if bad:
+        _say(f"{job.name}: digests differ in {bad}; localising with the sampled oracle check")
+        check_sampled(job, out, n_rho, n_dep, seed)
+        raise AssertionError(f"{job.name}: whole-output digests differ from the oracle's in {bad}")
+    _say(f"{job.name}: rho, dep, delta and labels equal the oracle's, all {job.n} points")
     return out
 
 
-def test_blobs_1m_sampled(dpc):
+def test_blobs_1m_whole(dpc):
     check_full_size(dpc, inputs.blobs_1m())
 
 
-def test_walks_4m_sampled(dpc):
+def test_walks_4m_whole(dpc):
     check_full_size(dpc, inputs.walks_4m(), n_rho=1000, n_dep=40)
+
+
+def test_reuse_grid_is_checked(dpc):
+    """DPC_REUSE_GRID with a workspace that holds no grid of these inputs computes
+    nothing (outputs untouched) and reports DPC_EINVAL; a reused grid keeps the
+    out-of-range status of its build."""
+    job = inputs.blob_job(81, 3000, 3, 5, 500.0, 2000.0, 0.05)
+    t = torch.from_numpy(job.pts).cuda()
+    n = job.n
+    rho = dpc.dpc_density(t, job.d_cut)
+    torch.cuda.synchronize()
+    for case in ("fresh workspace", "other points", "other cut-off"):
+        _say(f"reuse check: {case}")
+        ws = dpc.workspace(n, job.d, job.d_cut)
+        ws.zero_()
+        pts = t
+        if case != "fresh workspace":
+            dpc.dpc_density(t.clone() if case == "other points" else t,
+                            job.d_cut * (1.5 if case == "other cut-off" else 1.0), ws=ws)
+            dpc.dpc_sync_status(ws)
+        dep = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        delta = torch.full((n,), -7.0, dtype=torch.float64, device="cuda")
+        dpc.dpc_dependent(pts, job.d_cut, rho, dep=dep, delta=delta, flags=dpc.DPC_REUSE_GRID, ws=ws)
+        with pytest.raises(dpc.DpcError) as e:
+            dpc.dpc_sync_status(ws)
+        assert e.value.status == dpc.DPC_EINVAL, case
+        assert (dep.cpu().numpy() == -7).all() and (delta.cpu().numpy() == -7.0).all(), case
+    _say("reuse check: out-of-range status kept")
+    bad = job.pts.copy()
+    bad[5, 2] = 131072 + 77
+    tb = torch.from_numpy(bad).cuda()
+    ws = dpc.workspace(n, job.d, job.d_cut)
+    rho_b = dpc.dpc_density(tb, job.d_cut, ws=ws)
+    dep, delta = dpc.dpc_dependent(tb, job.d_cut, rho_b, flags=dpc.DPC_REUSE_GRID, ws=ws)
+    with pytest.raises(dpc.DpcError) as e:
+        dpc.dpc_sync_status(ws)
+    assert e.value.status == dpc.DPC_ERANGE
+    want = oracle_run(np.clip(bad, 0, 131071), job.d_cut, job.rho_min, job.delta_min)
+    assert np.array_equal(rho_b.cpu().numpy(), want["rho"])
+    assert np.array_equal(dep.cpu().numpy(), want["dep"])
+    assert np.array_equal(delta.cpu().numpy().view(np.int64), want["delta"].view(np.int64))
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_kernel_forms_single_job(dpc, lanes):
+    """Both kernel forms (64-query tasks, one query per lane) on one job through a
+    one-job batch with that option, against the oracle."""
+    for d in (2, 3, 4, 6):
+        job = inputs.blob_job(90 + d, 4000, d, 6, 500.0, 2500.0, 0.05)
+        _say(f"kernel form {lanes}: d={d}")
+        b = dpc.Batch([(torch.from_numpy(job.pts).cuda(), job.d_cut, job.rho_min, job.delta_min)],
+                      [dpc.Tuning.make(lanes=lanes)])
+        b.run()
+        b.sync_status()
+        got = {k: v.cpu().numpy() for k, v in b.out[0].items()}
+        got["ncenters"] = int(got["ncenters"][0])
+        b.close()
+        compare(got, oracle_run(job.pts, job.d_cut, job.rho_min, job.delta_min), ctx=f"lanes={lanes} d={d}")

@@ -56,7 +56,7 @@ def test_served_results_equal_alone(mods, roomy, slots):
                   for q in reqs if q.kind == "new")
     budget = 64 << 30 if roomy else int(1.3 * biggest)
     _say(f"serving {len(reqs)} requests, budget {budget >> 20} MiB, {slots} slots")
-    srv = serve.Server(budget_bytes=budget, slots=slots)
+    srv = serve.Server(budget_bytes=budget, slots=slots, relabel_slots=0 if slots == 3 else 1)
     srv.run(reqs)
     if not roomy:
         assert srv.stats["evicted"] > 0, "the small budget must force evictions"
@@ -81,3 +81,57 @@ def test_served_results_equal_alone(mods, roomy, slots):
     summary = serve.latency_summary(reqs)
     _say(f"latency {summary}, stats {dict(srv.stats)}")
     assert summary["new"]["count"] == sum(1 for q in reqs if q.kind == "new")
+
+
+def _make_job(spec):
+    return spec.make()
+
+
+def test_served_jobs_vs_oracle_digests(mods):
+    """The serving trace with new jobs of up to 200,000 points (d 2..8): every new
+    job's rho, dep, delta and labels against the oracle's digests (written by an
+    oracle-only script), and every re-threshold's labels against the oracle's
+    labelling of the job's (so verified) rho, dep and delta.  Re-thresholds run on
+    their own slot."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    from tests import digests
+
+    dpc, serve = mods
+    rec = digests.load().get("serve_test")
+    if rec is None:
+        pytest.skip("no oracle digests stored for the serving trace")
+    trace = inputs.serve_trace(**rec["trace"])
+    specs = [r.spec for r in trace if r.kind == "new"]
+    _say(f"drawing {len(specs)} served jobs")
+    with cf.ProcessPoolExecutor(16, mp_context=mp.get_context("spawn")) as ex:
+        jobs = dict(zip((sp.seed for sp in specs), ex.map(_make_job, specs, chunksize=2)))
+    reqs = serve.trace_requests(trace, lambda spec: jobs[spec.seed])
+    srv = serve.Server(budget_bytes=64 << 30, slots=4, relabel_slots=1, keep_outputs=True)
+    _say(f"serving {len(reqs)} requests")
+    srv.run(reqs)
+    by_key = {}
+    for q in reqs:
+        if q.kind != "new":
+            continue
+        want = rec["jobs"][str(q.seed)]
+        assert want["input"] == digests.input_digest(jobs[q.seed])[:16]
+        got = {"rho": q.rho.numpy(), "dep": q.dep.numpy(), "delta": q.delta.numpy(), "label": q.labels.numpy(),
+               "ncenters": int(q.ncenters[0])}
+        dg = digests.output_digests(got, short=16)
+        bad = [f for f in (*digests.OUT_KEYS, "ncenters") if dg[f] != want[f]]
+        assert not bad, f"new job {q.rid} (seed {q.seed}, n={want['n']}, d={want['d']}): {bad} differ from the oracle"
+        by_key[q.job_key] = got
+    relabels = 0
+    for q in reqs:
+        if q.kind != "rethreshold" or q.dropped:
+            continue
+        src = by_key[q.job_key]
+        lab, nc = scan.labels(src["rho"], src["dep"], src["delta"], q.rho_min, q.delta_min)
+        assert np.array_equal(q.labels.numpy(), lab), f"re-threshold {q.rid}"
+        assert int(q.ncenters[0]) == nc
+        relabels += 1
+    summary = serve.latency_summary(reqs)
+    _say(f"{len(by_key)} new jobs and {relabels} re-thresholds equal the oracle; latency {summary}")
+    assert relabels > 0
