@@ -108,6 +108,26 @@ dpc_status dpc_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32
                    double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
                    int64_t *ncenters, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * dpc_run for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and outputs as dpc_run, with the scratch space in a static device
+ * array of DPC_STATIC_SCRATCH_BYTES that each GPU holds from the first call on it
+ * until the process ends.  It calls no allocating routine.
+ *   status  optional device uint32 output (NULL: not written): the device-detected
+ *           status of this call, bit 0 a coordinate out of range (clamped), bit 1
+ *           inconsistent input (as reported by dpc_sync_status for dpc_run)
+ * Errors: those of dpc_run, and DPC_EWORKSPACE when dpc_workspace_bytes(n, d, d_cut)
+ * exceeds DPC_STATIC_SCRATCH_BYTES (nothing is enqueued).  The stream must belong to
+ * the current device.  Every call on one GPU uses that GPU's one array and clears
+ * what it needs itself: calls on one GPU must not overlap (their kernels would race
+ * on the array), so issue them on one stream or synchronise between them.
+ */
+#define DPC_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+dpc_status dpc_run_static(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                          double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
+                          int64_t *ncenters, uint32_t *status, void *stream);
+
 /* Minimum workspace of dpc_label called on its own (the device status header). */
 #define DPC_LABEL_WS_BYTES 256
 

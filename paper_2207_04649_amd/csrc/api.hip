@@ -420,6 +420,44 @@ void fill_plan_info(const Plan &p, dpc_plan_info *out) {
   out->lanes = p.lanes;
 }
 
+// ---- the static scratch array of dpc_run_static ----
+//
+// One array per GPU (each device holds its own copy of a __device__ variable),
+// kept until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: the device address comes from hipGetSymbolAddress, looked up
+// once per device with that device current, and only that address is ever handed
+// to kernels.
+constexpr size_t kStaticScratchBytes = size_t(DPC_STATIC_SCRATCH_BYTES);
+static_assert(kStaticScratchBytes % 256 == 0, "whole 256-byte slots");
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on first use).
+dpc_status static_scratch(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(DPC_EDEVICE, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return device_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u)) return fail(DPC_EDEVICE, "static scratch misaligned");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DPC_OK;
+}
+
+// The device status word of a workspace, copied to the caller's memory.
+__global__ void k_copy_status(const DevHeader *hdr, uint32_t *out) {
+  if (threadIdx.x == 0) *out = hdr->status;
+}
+
 dpc_status check_job(const dpc_job &j) {
   if (!j.pts || !j.rho || !j.dep || !j.delta || !j.label || !j.ncenters) return fail(DPC_EINVAL, "null pointer");
   if (j.n < 1 || j.n >= DPC_MAX_POINTS) return fail(DPC_EINVAL, "n must be in [1, 2^27)");
@@ -758,6 +796,33 @@ dpc_status dpc_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32
   hipError_t e = launch_label(n, rho, dep, delta, rho_min, delta_min, label, ncenters, w.hdr, s);
   if (e != hipSuccess) return device_fail(e, "label kernels");
   return DPC_OK;
+}
+
+dpc_status dpc_run_static(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                          double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
+                          int64_t *ncenters, uint32_t *status, void *stream) {
+  // Every check dpc_run makes, and the size check, come before any HIP call.
+  if (!pts) return fail(DPC_EINVAL, "null pointer argument");
+  Plan p;
+  if (n < 1 || n >= DPC_MAX_POINTS) return fail(DPC_EINVAL, "n must be in [1, 2^27)");
+  if (d < 1 || d > DPC_MAX_DIM) return fail(DPC_EINVAL, "d must be in [1, 8]");
+  if (!std::isfinite(d_cut) || !(d_cut > 0.0)) return fail(DPC_EINVAL, "d_cut must be finite and > 0");
+  if (!make_plan(n, d, d_cut, nullptr, &p)) return fail(DPC_EINVAL, "no plan for these sizes");
+  if (!rho || !dep || !delta || !label || !ncenters) return fail(DPC_EINVAL, "null pointer argument");
+  if (rho_min < 0) return fail(DPC_EINVAL, "rho_min must be >= 0");
+  if (std::isnan(delta_min) || !(delta_min > d_cut)) return fail(DPC_EINVAL, "delta_min must exceed d_cut");
+  if (p.total > kStaticScratchBytes)
+    return fail(DPC_EWORKSPACE, ("problem needs " + std::to_string(p.total) + " bytes of scratch; the static array "
+                                 "holds " + std::to_string(kStaticScratchBytes)).c_str());
+  void *ws = nullptr;
+  dpc_status st = static_scratch(&ws);
+  if (st != DPC_OK) return st;
+  st = dpc_run(pts, n, d, d_cut, rho_min, delta_min, rho, dep, delta, label, ncenters, ws, p.total, stream);
+  if (st != DPC_OK || !status) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DPC_LAUNCH((k_copy_status), 1, kWave, s, static_cast<const DevHeader *>(ws), status);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? DPC_OK : device_fail(e, "status copy");
 }
 
 void dpc_profile_enable(int32_t level) {

@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
             "dpc_dependent": (I32, [P, I64, I32, D, P, P, P, U32, P, SZ, P]),
             "dpc_label": (I32, [I64, P, P, P, I32, D, P, P, P, SZ, P]),
             "dpc_run": (I32, [P, I64, I32, D, I32, D, P, P, P, P, P, P, SZ, P]),
+            "dpc_run_static": (I32, [P, I64, I32, D, I32, D, P, P, P, P, P, P, P]),
             "dpc_sync_status": (I32, [P, P]),
             "dpc_last_error": (ctypes.c_char_p, []),
             "dpc_version": (I32, []),
@@ -222,6 +223,31 @@ def dpc_run(pts: torch.Tensor, d_cut: float, rho_min: int, delta_min: float, ws:
     ws = workspace(n, d, d_cut, dev) if ws is None else ws
     _check(lib().dpc_run(_ptr(pts), n, d, float(d_cut), int(rho_min), float(delta_min), _ptr(rho), _ptr(dep),
                          _ptr(delta), _ptr(label), _ptr(ncent), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def dpc_run_static(pts: torch.Tensor, d_cut: float, rho_min: int, delta_min: float, out: dict,
+                   status: torch.Tensor | None = None, stream=None) -> dict:
+    """dpc_run with the library's static scratch array (no workspace, no allocation).
+
+    ``out`` must hold preallocated rho, dep, delta, label and ncenters tensors (as
+    dpc_run fills them); ``status``, if given, is a 1-element int32 device tensor
+    that receives the device status word.
+    """
+    n, d = _pts(pts)
+    _need(out["rho"], torch.int32, (n,), "rho")
+    _need(out["dep"], torch.int32, (n,), "dep")
+    _need(out["delta"], torch.float64, (n,), "delta")
+    _need(out["label"], torch.int32, (n,), "label")
+    _need(out["ncenters"], torch.int64, (1,), "ncenters")
+    if status is not None:
+        _need(status, torch.int32, (1,), "status")
+    _check(lib().dpc_run_static(_ptr(pts), n, d, float(d_cut), int(rho_min), float(delta_min), _ptr(out["rho"]),
+                                _ptr(out["dep"]), _ptr(out["delta"]), _ptr(out["label"]), _ptr(out["ncenters"]),
+                                _ptr(status), _stream(stream)))
     return out
 
 

@@ -27,6 +27,8 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (&(x))
 
 typedef int hipError_t;
 typedef void *hipStream_t;
@@ -328,5 +330,13 @@ inline hipError_t hipEventElapsedTime(float *t, hipEvent_t, hipEvent_t) {
   return hipSuccess;
 }
 inline hipError_t hipEventDestroy(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipGetDevice(int *d) {
+  *d = 0;
+  return hipSuccess;
+}
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) {
+  *p = const_cast<void *>(sym);
+  return hipSuccess;
+}
 
 #define DPC_LAUNCH(K, G, B, S, ...) ::emu::launch((G), (B), [&]() { DPC_STRIP K(__VA_ARGS__); })

@@ -146,3 +146,19 @@ def test_plan_options_are_checked_and_applied():
     assert dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(0, 1)]))["stages"] == 1  # ball stage
     with pytest.raises(dpc.DpcError):
         dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(1, 99)]))
+
+
+def test_static_entry_rejects_before_any_device_call():
+    """dpc_run_static checks its arguments and the scratch size on the host."""
+    L = dpc.lib()
+    P = ctypes.c_void_p
+    fake = P(4096)
+    args = lambda n, d, dc, rm, dm: (fake, n, d, dc, rm, dm, fake, fake, fake, fake, fake, P(0), P(0))  # noqa: E731
+    assert L.dpc_run_static(P(0), 10, 2, 1.0, 1, 2.0, fake, fake, fake, fake, fake, P(0), P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_run_static(*args(0, 2, 1.0, 1, 2.0)) == dpc.DPC_EINVAL
+    assert L.dpc_run_static(*args(10, 2, 3.0, 1, 2.0)) == dpc.DPC_EINVAL  # delta_min <= d_cut
+    assert L.dpc_run_static(*args(10, 2, 1.0, -1, 2.0)) == dpc.DPC_EINVAL
+    big = 4_000_000
+    assert dpc.dpc_workspace_bytes(big, 4, 1500.0) > dpc.STATIC_SCRATCH_BYTES
+    assert L.dpc_run_static(*args(big, 4, 1500.0, 1, 9000.0)) == dpc.DPC_EWORKSPACE
+    assert b"static array" in L.dpc_last_error()
