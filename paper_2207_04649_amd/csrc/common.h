@@ -238,6 +238,21 @@ inline unsigned blocks_for(int64_t items, int per_block) {
 #define DPC_LAUNCH(K, G, B, S, ...) DPC_STRIP K<<<(G), (B), 0, (S)>>>(__VA_ARGS__)
 #endif
 
+// Fewest waves per SIMD a kernel is compiled for (the compiler caps its
+// registers to fit them).
+#ifndef DPC_WAVES
+#define DPC_WAVES(n) __attribute__((amdgpu_waves_per_eu(n)))
+#endif
+#ifndef DPC_DENSITY_WAVES
+#define DPC_DENSITY_WAVES 1
+#endif
+#ifndef DPC_SEARCH_WAVES
+#define DPC_SEARCH_WAVES 1
+#endif
+#ifndef DPC_RING_WAVES
+#define DPC_RING_WAVES 8
+#endif
+
 // Read-only global memory seen through the constant address space: uniform loads
 // from it become scalar (SMEM) loads.  Only for data no kernel writes while it runs.
 #ifndef DPC_CONST

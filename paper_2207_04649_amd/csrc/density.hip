@@ -118,6 +118,8 @@ __device__ __forceinline__ void density_lanes(Blk blk, const Plan &p, const Ws &
   const int64_t R1 = p.R - 1;  // D2 <= R - 1 is inside the ball
   const int K = p.K0;
   const int nrow = int(window_rows(p, K));
+  __shared__ uint2 queue_all[kWalkQueue * kBlock];  // each lane's queue of row ranges
+  uint2 *queue = queue_all + threadIdx.x;
   uint64_t work = 0;  // the lane's candidate tests (profiling)
   for (int64_t q = thread_index(blk); q < p.n; q += grid_threads(blk)) {
     LaneGeom<D> g;
@@ -129,14 +131,14 @@ __device__ __forceinline__ void density_lanes(Blk blk, const Plan &p, const Ws &
     }
     uint32_t count = 0;
     // one candidate: inside the ball or not
-    auto test = [&](uint32_t j) {
+    auto test = [&](uint32_t j, bool take) {
       if (MODE == kModeP16) {
         uint32_t cw[W];
         load_words<W>(w.spk + int64_t(j) * W, cw);
         int32_t acc = dot2_self_v(pk_sub16(qk[0], cw[0]), negR);
 #pragma unroll
         for (int k = 1; k < W; ++k) acc = dot2_self_v(pk_sub16(qk[k], cw[k]), acc);
-        count += uint32_t(acc) >> 31;
+        count += take ? uint32_t(acc) >> 31 : 0u;
       } else {
         int64_t d2 = 0;
 #pragma unroll
@@ -144,20 +146,16 @@ __device__ __forceinline__ void density_lanes(Blk blk, const Plan &p, const Ws &
           const int64_t df = int64_t(g.x[k] - w.spts[int64_t(j) * D + k]);
           d2 += df * df;
         }
-        count += d2 <= R1 ? 1u : 0u;
+        count += (take && d2 <= R1) ? 1u : 0u;
       }
     };
     bool done = false;
     if constexpr (D <= 4) {
       if (K == 1 && p.gm == D) {  // compile-time rows (3^(D-1) of them)
-        auto visit = [&](uint32_t b, uint32_t e) {
-          work += e - b;
-          for (uint32_t j = b; j < e; ++j) test(j);
-        };
         if (MODE == kModeP16)
-          walk_k1<D, uint32_t>(p, g, w.cnt, [&]() { return uint32_t(R1); }, visit);
+          work += walk_k1<D, uint32_t, true>(p, g, w.cnt, queue, [&]() { return uint32_t(R1); }, test);
         else
-          walk_k1<D, int64_t>(p, g, w.cnt, [&]() { return R1; }, visit);
+          work += walk_k1<D, int64_t, true>(p, g, w.cnt, queue, [&]() { return R1; }, test);
         done = true;
       }
     }
@@ -175,7 +173,7 @@ __device__ __forceinline__ void density_lanes(Blk blk, const Plan &p, const Ws &
 #pragma unroll
         for (int c = 0; c < kLaneRowChunk; ++c) {
           work += ee[c] - bb[c];
-          for (uint32_t j = bb[c]; j < ee[c]; ++j) test(j);
+          for (uint32_t j = bb[c]; j < ee[c]; ++j) test(j, true);
         }
       }
     }
@@ -198,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_density(Plan p, Ws w) {
 }
 
 template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_density_lanes(Plan p, Ws w) {
+__global__ __launch_bounds__(kBlock) DPC_WAVES(DPC_DENSITY_WAVES) void k_density_lanes(Plan p, Ws w) {
   density_lanes<D, MODE>(xcd_blk(), p, w);
 }
 

@@ -158,6 +158,8 @@ __device__ __forceinline__ void search_lanes(Blk blk, const Plan &p, const Ws &w
   const int64_t C = ball ? p.R - 1 : INT64_MAX;
   const int nrow = int(window_rows(p, K));
   const uint4 *srec = w.srec;
+  __shared__ uint2 queue_all[kWalkQueue * kBlock];  // each lane's queue of row ranges
+  uint2 *queue = queue_all + threadIdx.x;
   uint64_t work = 0;  // the lane's candidate tests (profiling)
   for (int64_t q = thread_index(blk); q < p.n; q += grid_threads(blk)) {
     LaneGeom<D> geo;
@@ -171,7 +173,7 @@ __device__ __forceinline__ void search_lanes(Blk blk, const Plan &p, const Ws &w
     // p16: key (D2 << 32) | id while searching; i64: (D2 << 27) | id throughout
     uint64_t best = kNoKey;
     // one candidate: the rank test and the (D2, id) minimum
-    auto consider = [&](uint32_t j) {
+    auto consider = [&](uint32_t j, bool take) {
       uint64_t kj, key;
       uint32_t cw[W];
       if (MODE == kModeP16 && W <= 2 && srec) {  // words and rank key in one load
@@ -197,23 +199,19 @@ __device__ __forceinline__ void search_lanes(Blk blk, const Plan &p, const Ws &w
         }
         key = (uint64_t(d2) << kIdBits) | uint32_t(~uint32_t(kj));
       }
-      best = (kj > Ki && key < best) ? key : best;
+      best = (take && kj > Ki && key < best) ? key : best;
     };
     bool done = false;
     if constexpr (D <= 4) {
       if (K == 1 && p.gm == D) {  // compile-time rows
-        auto visit = [&](uint32_t b, uint32_t e) {
-          work += e - b;
-          for (uint32_t j = b; j < e; ++j) consider(j);
-        };
         if (MODE == kModeP16) {  // squared gaps of a packed-path window stay below 2^31
           auto clip = [&]() {
             return uint32_t(best == kNoKey ? (ball ? uint64_t(C) : uint64_t(UINT32_MAX)) : min(uint64_t(C), best >> 32));
           };
-          walk_k1<D, uint32_t>(p, geo, w.cnt, clip, visit);
+          work += walk_k1<D, uint32_t, false>(p, geo, w.cnt, queue, clip, consider);
         } else {
           auto clip = [&]() { return best == kNoKey ? C : min(C, int64_t(best >> kIdBits)); };
-          walk_k1<D, int64_t>(p, geo, w.cnt, clip, visit);
+          work += walk_k1<D, int64_t, false>(p, geo, w.cnt, queue, clip, consider);
         }
         done = true;
       }
@@ -233,7 +231,7 @@ __device__ __forceinline__ void search_lanes(Blk blk, const Plan &p, const Ws &w
 #pragma unroll
         for (int c = 0; c < kLaneRowChunk; ++c) {
           work += ee[c] - bb[c];
-          for (uint32_t j = bb[c]; j < ee[c]; ++j) consider(j);
+          for (uint32_t j = bb[c]; j < ee[c]; ++j) consider(j, true);
         }
       }
     }
@@ -384,7 +382,10 @@ __device__ __forceinline__ uint64_t exact_d2_v(const int32_t *a, const int32_t *
 // is final once its best candidate is strictly closer than the exterior of the
 // block; it goes to the prefix scan when the passes have cost more than that
 // scan would.
-constexpr int kRingRows = 4;  // rows per lane per round
+#ifndef DPC_RING_ROWS
+#define DPC_RING_ROWS 2
+#endif
+constexpr int kRingRows = DPC_RING_ROWS;  // rows per lane per round
 
 struct SegLds {
   uint32_t off[kWave];                // exclusive prefix of the lanes' candidate counts
@@ -718,12 +719,12 @@ __global__ __launch_bounds__(kBlock) void k_search(Plan p, Ws w, int K, int grou
 // nothing to do, so their blocks keep the dispatcher's order (renumbering would
 // put all the work on one XCD).
 template <int D, int MODE>
-__global__ __launch_bounds__(kBlock) void k_search_lanes(Plan p, Ws w, int K) {
+__global__ __launch_bounds__(kBlock) DPC_WAVES(DPC_SEARCH_WAVES) void k_search_lanes(Plan p, Ws w, int K) {
   search_lanes<D, MODE>(xcd_blk(), p, w, K);
 }
 __global__ __launch_bounds__(kBlock) void k_collect(Plan p, Ws w) { collect_body(grid_blk(), p, w.flag, w.unres, w.hdr); }
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_ringk(Plan p, Ws w, int k_start) {
+__global__ __launch_bounds__(kBlock) DPC_WAVES(DPC_RING_WAVES) void k_ringk(Plan p, Ws w, int k_start) {
   ringk_body<D>(grid_blk(), p, w, k_start);
 }
 template <int D>

@@ -172,7 +172,7 @@ __device__ __forceinline__ void task_span(const Plan &p, TaskGeom<D> &g, int32_t
 // within K, clipped to a squared radius.  The row offsets are the same for every
 // lane (a wave-uniform walk); the cell ranges differ per lane.
 
-constexpr int kLaneRowChunk = 8;  // window rows whose cell ranges a lane loads before scanning them
+constexpr int kLaneRowChunk = 8;  // window rows whose cell ranges a lane loads before scanning them (K > 1)
 
 template <int D>
 struct LaneGeom {
@@ -308,20 +308,37 @@ __device__ __forceinline__ bool lane_row(const Plan &p, const LaneGeom<D> &g, co
 
 constexpr int ipow3(int e) { return e <= 0 ? 1 : 3 * ipow3(e - 1); }
 
+// Rows of a radius-1 window whose candidate ranges one lane queues in LDS before
+// testing them as one stream (a plane of the window when D = 4).
+template <int D>
+constexpr int walk_chunk() {
+  return ipow3(D - 1) < 9 ? ipow3(D - 1) : 9;
+}
+constexpr int kWalkQueue = 9;  // LDS queue entries per lane (walk_chunk<D>() <= this)
+
+
 // The radius-1 window of a lane's cell when every coordinate is indexed (gm ==
 // D), with compile-time row offsets: 3^(D-1) rows, the lane's own row first
-// (digits run 0, -1, +1), in chunks of kLaneRowChunk whose cell ranges are
-// loaded together (one 16-byte load of start[x - 1 .. x + 2] per row).  `clip()`
-// gives the squared radius, read once per chunk (a smaller one later only
-// leaves extra candidates); `visit(b, e)` scans the candidates of a row's range.
+// (digits run 0, -1, +1).  A chunk of walk_chunk<D>() rows has its cell ranges
+// loaded together (two words of start[x - 1 .. x + 2] per row); the non-empty
+// ranges go to the lane's LDS queue (entries `queue[k * kBlock]`, k <
+// kWalkQueue) and their candidates are then tested as one stream, so a wave
+// runs as many test steps as its busiest lane has candidates in the chunk (not
+// the sum over rows of each row's busiest lane); with PAIR two candidates per
+// step, their loads in flight together.  `clip()` gives the squared
+// radius, read once per chunk (a smaller one later only leaves extra
+// candidates); `test(j, take)` tests candidate j and keeps the result only when
+// `take` (its loads run either way, on a valid j).  Returns the candidates tested.
 // T holds squared gaps and radii: 32 bits when they are known to stay below
 // 2^31 (the packed path's windows), else 64.
-template <int D, class T, class ClipF, class VisitF>
-__device__ __forceinline__ void walk_k1(const Plan &p, const LaneGeom<D> &g, const uint32_t *__restrict__ start,
-                                        ClipF clip_fn, VisitF visit) {
+template <int D, class T, bool PAIR, class ClipF, class TestF>
+__device__ __forceinline__ uint32_t walk_k1(const Plan &p, const LaneGeom<D> &g, const uint32_t *__restrict__ start,
+                                            uint2 *queue, ClipF clip_fn, TestF test) {
   constexpr int RD = D - 1;          // row dimensions
   constexpr int NR = ipow3(RD);      // rows
   constexpr int RA = RD > 0 ? RD : 1;
+  constexpr int CH = walk_chunk<D>();
+  static_assert(CH <= kWalkQueue, "queue too short for a chunk");
   const int32_t L = p.L, nc = p.nc;
   T gy[RA][3];
   int32_t part[RA][3];
@@ -344,41 +361,89 @@ __device__ __forceinline__ void walk_k1(const Plan &p, const LaneGeom<D> &g, con
   const T gsl = gl * gl, gsh = gh * gh;
   const bool lo_in = cs >= 1, hi_in = cs + 1 < nc;
   const uint32_t *base = start + (cs - 1);
+  uint32_t tested = 0;
 #pragma unroll
-  for (int r0 = 0; r0 < NR; r0 += kLaneRowChunk) {
+  for (int r0 = 0; r0 < NR; r0 += CH) {
     const T clip = clip_fn();
-    uint4 v[kLaneRowChunk];
-    T dy2[kLaneRowChunk];
-    bool ok[kLaneRowChunk];
+    uint32_t vb[CH], ve[CH];
+    T dy2[CH];
+    bool ok[CH];
 #pragma unroll
-    for (int c = 0; c < kLaneRowChunk; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int r = r0 + c;
-      if (r < NR) {
-        T dy = 0;
-        bool in = true;
-        int32_t rowk = 0;
+      T dy = 0;
+      bool in = true;
+      int32_t rowk = 0;
 #pragma unroll
-        for (int t = 0; t < RD; ++t) {
-          const int i = (r / ipow3(t)) % 3;
-          dy += gy[t][i];
-          in = in && okd[t][i];
-          rowk += part[t][i];
+      for (int t = 0; t < RD; ++t) {
+        const int i = (r / ipow3(t)) % 3;
+        dy += gy[t][i];
+        in = in && okd[t][i];
+        rowk += part[t][i];
+      }
+      dy2[c] = dy;
+      ok[c] = in && dy <= clip;
+      // the row's range: from start[x - 1] when cell x - 1 is within the radius
+      // (else start[x]) to start[x + 2] when cell x + 1 is (else start[x + 1])
+      const int bo = (lo_in && gsl + dy <= clip) ? 0 : 1, eo = (hi_in && gsh + dy <= clip) ? 3 : 2;
+      vb[c] = ve[c] = 0;
+      if (ok[c]) {
+        vb[c] = base[rowk + bo];
+        ve[c] = base[rowk + eo];
+      }
+    }
+    uint32_t m = 0, total = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const uint32_t b = vb[c], e = ve[c];
+      if (ok[c] && b < e) {
+        queue[m * kBlock] = make_uint2(b, e);
+        ++m;
+        total += e - b;
+      }
+    }
+    if (PAIR) {
+      // two candidates per step (both loads in flight together); the next queued
+      // range is read one refill ahead
+      uint32_t j = 0, e = 0, k = 1;
+      uint2 nx = make_uint2(0u, 0u);
+      if (m > 0) nx = queue[0];
+      for (uint32_t t = 0; t < total; t += 2) {
+        if (j == e) {
+          j = nx.x;
+          e = nx.y;
+          if (k < m) nx = queue[k * kBlock];
+          ++k;
         }
-        dy2[c] = dy;
-        ok[c] = in && dy <= clip;
-        v[c] = make_uint4(0u, 0u, 0u, 0u);
-        if (ok[c]) __builtin_memcpy(&v[c], base + rowk, 16);
+        const uint32_t j0 = j++;
+        const bool two = t + 1 < total;
+        if (two && j == e) {
+          j = nx.x;
+          e = nx.y;
+          if (k < m) nx = queue[k * kBlock];
+          ++k;
+        }
+        const uint32_t j1 = two ? j : j0;
+        j += two ? 1u : 0u;
+        test(j0, true);
+        test(j1, two);
+      }
+    } else {
+      uint32_t j = 0, e = 0, k = 0;
+      for (uint32_t t = 0; t < total; ++t) {
+        if (j == e) {  // the next queued range (never empty)
+          const uint2 r = queue[k * kBlock];
+          ++k;
+          j = r.x;
+          e = r.y;
+        }
+        test(j, true);
+        ++j;
       }
     }
-#pragma unroll
-    for (int c = 0; c < kLaneRowChunk; ++c) {
-      if (r0 + c < NR) {
-        const uint32_t b = (lo_in && gsl + dy2[c] <= clip) ? v[c].x : v[c].y;
-        const uint32_t e = (hi_in && gsh + dy2[c] <= clip) ? v[c].w : v[c].z;
-        if (ok[c] && b < e) visit(b, e);
-      }
-    }
+    tested += total;
   }
+  return tested;
 }
 
 // Squared distance from x to the outside of the block of cells within K of its

@@ -18,5 +18,8 @@ def build(out_dir: str, asan: bool = False) -> str:
            "-x", "none", os.path.join(HERE, "driver.cpp"), "-o", exe]
     if asan:
         cmd[1:1] = ["-fsanitize=address", "-fno-omit-frame-pointer"]
+    # extra -D options of the kernel sources (space-separated), e.g. to check a
+    # compile-time variant of a kernel
+    cmd[1:1] = os.environ.get("DPC_EMU_DEFINES", "").split()
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     return exe

@@ -26,6 +26,7 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+#define DPC_WAVES(n)
 #define __shared__ static
 #define __align__(n) alignas(n)
 #define HIP_SYMBOL(x) (&(x))
