@@ -371,17 +371,20 @@ __device__ __forceinline__ uint64_t exact_d2_v(const int32_t *a, const int32_t *
 }
 
 // Ring search for the points the search stages left open, one wave per point.
-// The searched block grows from the cells within k0 (the last stage's radius)
-// of the point's cell to k1 = 2 k0 (an annulus per pass, so a sparse
-// neighbourhood needs a logarithmic number of passes).  In every row of the
-// annulus the cell range is clipped to the cells that can still hold a point
-// within the best distance so far, and a row farther than that is skipped.  A
+// Each pass grows the searched block from the cells within k0 of the point's
+// cell (the last stage's radius) to k1 = 2 k0 (an annulus per pass, so a sparse
+// neighbourhood needs a logarithmic number of passes); the point is final once
+// its best candidate is strictly closer than the exterior of the block.  With a
+// candidate at squared distance b, a pass also leaves out the cells farther than
+// sqrt(b) from the point in some dimension; when that bound is tighter than the
+// block on every side, the pass has seen every cell within sqrt(b) of the point,
+// so every point closer than the best, and the point is final too.  In every
+// row the cell range is clipped to the cells that can still hold a point within
+// the best distance so far, and a row farther than that is skipped.  A
 // pass takes its rows kRingRows per lane at a time (their cell ranges loaded
-// together), flattens their candidates over the wave and tests two per lane at a
-// time, so a wide, mostly empty annulus costs few memory round trips.  The point
-// is final once its best candidate is strictly closer than the exterior of the
-// block; it goes to the prefix scan when the passes have cost more than that
-// scan would.
+// together), flattens their candidates over the wave and tests two per lane at
+// a time.  The point goes to the prefix scan when the passes have cost more than
+// that scan would.
 #ifndef DPC_RING_ROWS
 #define DPC_RING_ROWS 2
 #endif
@@ -392,10 +395,39 @@ struct SegLds {
   uint2 seg[kWave][2 * kRingRows];    // each lane's row pieces: {first position, count}
 };
 
+// A bound r >= sqrt(v) (v < 2^40) from the float square root: the conversion and
+// the root are each within a relative 2^-23 of exact, so a 2^-20 margin and one
+// unit cover them.
+__device__ __forceinline__ int32_t sqrt_ceil_bound(uint64_t v) {
+  const float f = __builtin_sqrtf(float(v));
+  return int32_t(f * (1.0f + 0x1p-20f)) + 1;
+}
+
+// Gap from coordinate x to cell cc (side L) along one dimension, 32-bit.
+__device__ __forceinline__ uint32_t cell_gap32(int32_t x, int32_t cc, int32_t L) {
+  const int32_t lo = cc * L, hi = lo + L - 1;
+  return uint32_t(x < lo ? lo - x : (x > hi ? x - hi : 0));
+}
+
+// Exact squared distance: each |dx| < 2^31, its square formed as a 32 x 32 -> 64
+// bit product.
+template <int D>
+__device__ __forceinline__ uint64_t exact_d2_u(const int32_t *a, const int32_t *b) {
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int32_t df = a[k] - b[k];
+    const uint32_t ad = uint32_t(df < 0 ? -df : df);
+    s += uint64_t(ad) * uint64_t(ad);
+  }
+  return s;
+}
+
 template <int D>
 __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, int k_start) {
   __shared__ SegLds lds_all[kWavesPerBlock];
   SegLds &lds = lds_all[threadIdx.x / kWave];
+  constexpr int RA = D > 1 ? D - 1 : 1;
   const int lane = lane_id();
   if (grid_skipped(w.hdr)) return;
   const uint32_t nunres = uniform(as_const(&w.hdr->n_unres)[0]);
@@ -403,6 +435,8 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
   DPC_CONST(uint64_t) *sKc = as_const(w.sK);
   DPC_CONST(uint32_t) *unres = as_const(w.unres);
   DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
+  const int32_t L = p.L, nc = p.nc;
+  const int nr = p.gm - 1;  // row dimensions
 
   uint64_t work = 0;  // candidate tests (wave-uniform; profiling)
   const uint32_t nw = grid_waves(blk);
@@ -412,9 +446,10 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
 #pragma unroll
     for (int k = 0; k < D; ++k) {
       x[k] = uniform(spc[int64_t(q) * D + k]);
-      c[k] = x[k] / p.L;
+      c[k] = x[k] / L;
     }
-    const int32_t xs = uniform(spc[int64_t(q) * D + (p.gm - 1)]);  // coordinate along the strip dimension
+    const int32_t xs = uniform(spc[int64_t(q) * D + nr]);  // coordinate along the strip dimension
+    const int32_t cl = xs / L;
     const uint64_t Ki = uniform(sKc[q]);
     const int64_t rho = int64_t(Ki >> 32);
     uint64_t best = uniform(w.best[q]);
@@ -422,82 +457,105 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
     const int64_t budget = min(int64_t(prefix / kWave) + 2, int64_t(p.ring_cap));
     int64_t cost = 0;
     bool defer = false;
-    int32_t k0 = k_start;
+    int32_t k0 = k_start;  // -1: nothing searched yet
 
     for (;;) {
-      const int32_t k1 = k0 < 1 ? 1 : 2 * k0;  // k0 = -1: nothing searched yet
-      const int64_t side = 2 * int64_t(k1) + 1;
-      int64_t nrows = 1;
-      for (int t = 0; t < p.gm - 1; ++t) nrows *= side;
-      const uint64_t bestd2 = best >> kIdBits;  // huge when there is no best yet
-      for (int64_t rb = 0; rb < nrows; rb += int64_t(kWave) * kRingRows) {
+      // This pass: the cells of the box [lo, lo + ext) (row dimensions) x [sa, sb]
+      // (strip dimension) outside the block within k0 of the point's cell.
+      const bool has_best = best != kNoKey;
+      const int32_t k1 = k0 < 1 ? 1 : min(2 * k0, nc);
+      const int32_t rb = has_best ? sqrt_ceil_bound(best >> kIdBits) : 0;
+      bool covered = has_best;  // the radius bound is the tighter one on every side
+      auto box = [&](int32_t xt, int32_t ct, int32_t *a, int32_t *b) {
+        *a = max(ct - k1, 0);
+        *b = min(ct + k1, nc - 1);
+        if (has_best) {
+          const int32_t ra = max(xt - rb, 0) / L, rz = min(xt + rb, DPC_COORD_LIMIT - 1) / L;
+          covered = covered && (ra >= *a || *a == 0) && (rz <= *b || *b == nc - 1);
+          *a = max(*a, ra);
+          *b = min(*b, rz);
+        }
+      };
+      int32_t lo[RA], ext[RA];
+      uint32_t mg[RA];  // ceil(2^32 / ext): r / ext as a high product while r * ext < 2^32
+      uint64_t nrows = 1;
+      int32_t emax = 1;
+#pragma unroll
+      for (int t = 0; t < RA; ++t) {
+        lo[t] = 0;
+        ext[t] = 1;
+        mg[t] = 0;
+        if (t < nr) {
+          int32_t a, b;
+          box(x[t], c[t], &a, &b);
+          lo[t] = a;
+          ext[t] = b - a + 1;
+          mg[t] = ext[t] > 1 ? 0xFFFFFFFFu / uint32_t(ext[t]) + 1u : 0u;
+          nrows *= uint64_t(ext[t]);
+          emax = max(emax, ext[t]);
+        }
+      }
+      int32_t sa, sb;
+      box(xs, cl, &sa, &sb);
+      const bool fast_div = nrows * uint64_t(emax) < (uint64_t(1) << 32);
+      for (uint64_t r0b = 0; r0b < nrows; r0b += uint64_t(kWave) * kRingRows) {
+        const uint64_t bestd2 = best >> kIdBits;  // huge when there is no best yet
         uint2 sg[2 * kRingRows];
         uint32_t mine = 0;  // this lane's candidates in the round
 #pragma unroll
         for (int i = 0; i < kRingRows; ++i) {
           sg[2 * i] = make_uint2(0u, 0u);
           sg[2 * i + 1] = make_uint2(0u, 0u);
-          const int64_t r0 = rb + int64_t(i) * kWave + lane;
+          const uint64_t r0 = r0b + uint64_t(i) * kWave + uint64_t(lane);
           if (r0 < nrows) {
-            // row offsets: digits of r0 in base `side` (32-bit division while it fits)
-            int32_t off[D > 1 ? D - 1 : 1];
-            if (nrows <= int64_t(UINT32_MAX)) {
-              uint32_t r = uint32_t(r0);
-              const uint32_t us = uint32_t(side);
-#pragma unroll
-              for (int t = 0; t < D - 1; ++t) {
-                off[t] = int32_t(r % us) - k1;
-                r /= us;
-              }
-            } else {
-              int64_t r = r0;
-#pragma unroll
-              for (int t = 0; t < D - 1; ++t) {
-                off[t] = int32_t(r % side) - k1;
-                r /= side;
-              }
-            }
-            int64_t md = 0;
+            uint64_t md = 0;
             int32_t rowk = 0;  // row index of the cell table (ncells < 2^31)
-            bool ok = true, outer = false;
+            bool outer = k0 < 0;
+            uint32_t r32 = uint32_t(r0);
+            uint64_t r64 = r0;
 #pragma unroll
-            for (int t = 0; t < D - 1; ++t) {
-              if (t < p.gm - 1) {
-                const int32_t o = off[t];
-                const int32_t nb = c[t] + o;
-                ok = ok && nb >= 0 && nb < p.nc;
+            for (int t = 0; t < RA; ++t) {
+              if (t < nr) {
+                int32_t d;
+                if (fast_div) {
+                  const uint32_t qd = ext[t] > 1 ? __umulhi(r32, mg[t]) : r32;
+                  d = int32_t(r32 - qd * uint32_t(ext[t]));
+                  r32 = qd;
+                } else {
+                  d = int32_t(r64 % uint64_t(ext[t]));
+                  r64 /= uint64_t(ext[t]);
+                }
+                const int32_t nb = lo[t] + d;
+                const int32_t o = nb - c[t];
                 outer = outer || o > k0 || o < -k0;
-                rowk = rowk * p.nc + nb;
-                const int64_t gp = cell_gap(x[t], nb, p.L);
-                md += gp * gp;
+                rowk = rowk * nc + nb;
+                const uint32_t gp = cell_gap32(x[t], nb, L);
+                md += uint64_t(gp) * uint64_t(gp);
               }
             }
-            if (ok && uint64_t(md) <= bestd2) {
+            if (md <= bestd2) {
               // strip-dimension cells that can hold a point within the best distance
-              const int32_t cl = xs / p.L;
-              int32_t lo = max(cl - k1, 0), hi = min(cl + k1, p.nc - 1);
-              if (bestd2 < (uint64_t(1) << 38)) {
-                const int64_t rr = isqrt_floor(bestd2 - uint64_t(md));
-                const int32_t a = int32_t(max(int64_t(xs) - rr, int64_t(0)));
-                const int32_t c2 = int32_t(min(int64_t(xs) + rr, int64_t(DPC_COORD_LIMIT - 1)));
-                lo = max(lo, a / p.L);
-                hi = min(hi, c2 / p.L);
+              int32_t lo_s = sa, hi_s = sb;
+              if (bestd2 < (uint64_t(1) << 40)) {
+                const int32_t rr = sqrt_ceil_bound(bestd2 - md);
+                lo_s = max(lo_s, max(xs - rr, 0) / L);
+                hi_s = min(hi_s, min(xs + rr, DPC_COORD_LIMIT - 1) / L);
               }
-              const int32_t base = rowk * p.nc;
+              const int32_t base = rowk * nc;
               if (outer) {  // the whole row lies outside the block searched so far
-                if (lo <= hi) {
-                  const uint32_t b = w.cnt[base + lo];
-                  sg[2 * i] = make_uint2(b, w.cnt[base + hi + 1] - b);
+                if (lo_s <= hi_s) {
+                  const uint32_t b = w.cnt[base + lo_s];
+                  sg[2 * i] = make_uint2(b, w.cnt[base + hi_s + 1] - b);
                 }
               } else {  // two pieces: left and right of the searched block
-                const int32_t l_hi = min(hi, cl - k0 - 1), r_lo = max(lo, cl + k0 + 1);
-                if (lo <= l_hi) {
-                  const uint32_t b = w.cnt[base + lo];
+                const int32_t l_hi = min(hi_s, cl - k0 - 1), r_lo = max(lo_s, cl + k0 + 1);
+                if (lo_s <= l_hi) {
+                  const uint32_t b = w.cnt[base + lo_s];
                   sg[2 * i] = make_uint2(b, w.cnt[base + l_hi + 1] - b);
                 }
-                if (r_lo <= hi) {
+                if (r_lo <= hi_s) {
                   const uint32_t b = w.cnt[base + r_lo];
-                  sg[2 * i + 1] = make_uint2(b, w.cnt[base + hi + 1] - b);
+                  sg[2 * i + 1] = make_uint2(b, w.cnt[base + hi_s + 1] - b);
                 }
               }
             }
@@ -553,7 +611,7 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
           }
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const uint64_t key = (exact_d2_v<D>(x, y[h]) << kIdBits) | uint32_t(~uint32_t(kj[h]));
+            const uint64_t key = (exact_d2_u<D>(x, y[h]) << kIdBits) | uint32_t(~uint32_t(kj[h]));
             lbest = (have[h] && kj[h] > Ki && key < lbest) ? key : lbest;
           }
         }
@@ -561,18 +619,20 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
         const uint64_t wb = uniform(wave_min_u64(lbest));
         best = wb < best ? wb : best;
       }
-      if (cost >= budget) {  // the annulus is incomplete: only the prefix scan is exact now
+      if (cost >= budget) {  // the pass is incomplete: only the prefix scan is exact now
         defer = true;
         break;
       }
+      // Every cell within the starting best distance has been seen.
+      if (covered) break;
       // The searched block is now every cell within k1 of the point's cell (in
       // the grid dimensions; a gap in one of them bounds the full distance).
       int64_t gap = INT64_MAX;
 #pragma unroll
       for (int t = 0; t < D; ++t) {
         if (t < p.gm) {
-          if (c[t] - k1 >= 1) gap = min(gap, int64_t(x[t]) - int64_t(c[t] - k1) * p.L + 1);
-          if (c[t] + k1 <= p.nc - 2) gap = min(gap, int64_t(c[t] + k1 + 1) * p.L - int64_t(x[t]));
+          if (c[t] - k1 >= 1) gap = min(gap, int64_t(x[t]) - int64_t(c[t] - k1) * L + 1);
+          if (c[t] + k1 <= nc - 2) gap = min(gap, int64_t(c[t] + k1 + 1) * L - int64_t(x[t]));
         }
       }
       if (gap == INT64_MAX) break;  // the block covers the whole grid

@@ -48,6 +48,7 @@ struct alignas(8) uint2 {
 };
 inline uint4 make_uint4(unsigned x, unsigned y, unsigned z, unsigned w) { return uint4{x, y, z, w}; }
 inline uint2 make_uint2(unsigned x, unsigned y) { return uint2{x, y}; }
+inline unsigned __umulhi(unsigned a, unsigned b) { return unsigned((static_cast<unsigned long long>(a) * b) >> 32); }
 
 template <class T>
 inline T min(T a, T b) {
