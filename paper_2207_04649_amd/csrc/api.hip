@@ -27,11 +27,11 @@ std::vector<ProfRec> g_prof_recs;
 std::vector<ProfRec> g_prof_open;  // begins awaiting their end, per kernel id
 int g_prof_level = 0;
 // work counters of the last dependent search (profiling level 2)
-int64_t g_work[4] = {0, 0, 0, 0};
+int64_t g_work[5] = {0, 0, 0, 0, 0};
 // candidate distance tests of the last call's density, window search, ring search and prefix scan
 int64_t g_tests[4] = {0, 0, 0, 0};
 const char *kProfNames[kProfCount] = {"grid_build", "density", "rank_keys", "rank_sort", "search",
-                                      "ringk", "peaks", "finish", "label"};
+                                      "open_search", "ringk", "peaks", "finish", "label"};
 }  // namespace
 
 bool prof_on() { return g_prof_level > 0; }
@@ -251,6 +251,28 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
     p.stageMode[p.nstages] = (gm == d && p16) ? kModeP16 : kModeI64;
     ++p.nstages;
   }
+  // Lane form: a second window stage, of twice the first's radius, over the
+  // points the first leaves open; the ring search grows from its block.
+  p.openK = 0;
+  p.openMode = kModeI64;
+  if (p.lanes && p.stageK[0] >= 1) {
+    int K2 = 2 * p.stageK[0];
+    const int v = opt ? opt->open_radius : 0;
+    if (v < -1 || v > 16 || (v > 0 && v <= p.stageK[0])) return false;
+    if (v == -1) K2 = 0;
+    if (v > 0) K2 = v;
+    if (K2 > 16) K2 = 0;
+    int64_t rows = 1;  // the stage's rows stay below 2^20
+    for (int t = 0; t < gm - 1 && K2; ++t) rows *= 2 * K2 + 1;
+    if (rows > (int64_t(1) << 20)) {
+      if (v > 0) return false;
+      K2 = 0;
+    }
+    if (K2) {
+      p.openK = K2;
+      p.openMode = (gm == d && (int64_t(K2) + 1) * L <= E) ? kModeP16 : kModeI64;
+    }
+  }
   // Ring steps before the prefix scan: more in more dimensions, where rings
   // stay cheap longer than scanning a long density prefix.
   p.ring_cap = d <= 2 ? kRingCostCap : 4 * kRingCostCap;
@@ -368,6 +390,7 @@ hipError_t record_work(const Plan &p, const Ws &w, hipStream_t s) {
   g_work[1] = h.n_unres;
   g_work[2] = h.n_peaks;
   g_work[3] = prefix;
+  g_work[4] = p.openK ? h.n_ring : h.n_unres;
   for (int k = 0; k < 4; ++k) g_tests[k] = int64_t(h.work[k]);
   return hipSuccess;
 }
@@ -418,6 +441,7 @@ void fill_plan_info(const Plan &p, dpc_plan_info *out) {
   out->stages = p.nstages;
   out->grid_dims = p.gm;
   out->lanes = p.lanes;
+  out->open_radius = p.openK;
 }
 
 // ---- the static scratch array of dpc_run_static ----
@@ -490,7 +514,7 @@ struct dpc_batch {
   std::vector<size_t> ws_off;   // launch order: offset of each job's workspace
   Map maps[5];                  // one, pts, cells, strips, work
   size_t o_status = 0, o_jobs = 0, o_map[5][3] = {}, total = 0;
-  int32_t ngroups = 0, gdim[DPC_MAX_DIM] = {}, max_stages = 0;
+  int32_t ngroups = 0, gdim[DPC_MAX_DIM] = {}, max_stages = 0, any_open = 0;
   uint32_t gwork0[DPC_MAX_DIM] = {}, gwork1[DPC_MAX_DIM] = {};
   void *bound = nullptr;
 };
@@ -528,6 +552,7 @@ BatchMaps batch_maps(const dpc_batch &b, void *ws) {
     B.gwork1[g] = b.gwork1[g];
   }
   B.max_stages = b.max_stages;
+  B.any_open = b.any_open;
   return B;
 }
 
@@ -608,6 +633,7 @@ dpc_status dpc_batch_plan(const dpc_job *jobs, int32_t njobs, const dpc_tuning *
     }
     b->gwork1[b->ngroups - 1] = uint32_t(b->maps[kMapWork].vjob.size());
     b->max_stages = std::max(b->max_stages, p.nstages);
+    if (p.openK) b->any_open = 1;
   }
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -857,9 +883,10 @@ int32_t dpc_profile_report(char *buf, size_t len) {
   {
     char item[512];
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    std::snprintf(item, sizeof(item), ", \"work\": {\"tasks\": %lld, \"open\": %lld, \"peaks\": %lld, "
-                  "\"peak_prefix\": %lld, \"tests_density\": %lld, \"tests_search\": %lld, \"tests_ring\": %lld, "
-                  "\"tests_peaks\": %lld}", static_cast<long long>(g_work[0]), static_cast<long long>(g_work[1]),
+    std::snprintf(item, sizeof(item), ", \"work\": {\"tasks\": %lld, \"open\": %lld, \"ring\": %lld, "
+                  "\"peaks\": %lld, \"peak_prefix\": %lld, \"tests_density\": %lld, \"tests_search\": %lld, "
+                  "\"tests_ring\": %lld, \"tests_peaks\": %lld}", static_cast<long long>(g_work[0]),
+                  static_cast<long long>(g_work[1]), static_cast<long long>(g_work[4]),
                   static_cast<long long>(g_work[2]), static_cast<long long>(g_work[3]),
                   static_cast<long long>(g_tests[0]), static_cast<long long>(g_tests[1]),
                   static_cast<long long>(g_tests[2]), static_cast<long long>(g_tests[3]));

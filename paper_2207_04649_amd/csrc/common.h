@@ -48,7 +48,7 @@ struct DevHeader {
   uint32_t n_unres;       // points left open by the search stages
   uint32_t n_peaks;       // points left to the rank-prefix scan
   uint32_t skip;          // 1: the workspace holds no grid of this call's inputs; grid kernels do nothing
-  uint32_t pad0;
+  uint32_t n_ring;        // points left to the ring search by the open-point stage (Plan::openK)
   uint64_t stamp[kStampWords];  // the grid's identity (grid_stamp)
   uint64_t work[4];       // with Plan::count_work: candidate (query, point) distance tests of the
                           // density, window search, ring search and prefix scan kernels
@@ -78,6 +78,9 @@ struct Plan {
   int32_t lanes;     // 1: one query per lane with its own window (sparse data); 0: tasks of 64
                      // queries of one strip sharing a window's candidates (dense data)
   int32_t count_work; // 1: the kernels count their distance tests into DevHeader::work (profiling)
+  int32_t openK;     // lane form: radius of a second window stage over the points the first left
+                     // open (0: none; the ring search then starts from the first stage's block)
+  int32_t openMode;  // DistMode of that stage
   int64_t ncells;    // nc^gm
   int64_t nrows;     // nc^(gm-1)
   int64_t nstrips;   // nrows * nsx
@@ -93,7 +96,8 @@ struct Ws {
   uint32_t *cnt;     // [ncells + 1] cell counts, then cell starts (exclusive scan)
   uint32_t *bsum;    // scan block sums
   uint32_t *key;     // [n] cell key per id; after the id scatter, the id's cell-order position
-  uint32_t *slot;    // [n] slot within the cell (later: slot within the rho bucket)
+  uint32_t *slot;    // [n] slot within the cell (later: slot within the rho bucket; after the rank
+                     // sort, the points the open-point stage leaves to the ring search)
   int32_t *spts;     // [n][d] clamped coordinates in cell order
   uint32_t *spk;     // [n][words] packed low 16 bits of the coordinates, cell order
   int32_t *sid;      // [n] id at each cell-order position
@@ -174,6 +178,7 @@ struct BatchMaps {
   int32_t gdim[DPC_MAX_DIM];                       // dimension of each group
   uint32_t gwork0[DPC_MAX_DIM], gwork1[DPC_MAX_DIM];  // its work virtual blocks
   int32_t max_stages;
+  int32_t any_open;  // some job runs the open-point stage (Plan::openK)
 };
 
 // Blocks of a many-job launch over m (0: nothing to launch).

@@ -249,6 +249,311 @@ __device__ __forceinline__ void search_lanes(Blk blk, const Plan &p, const Ws &w
   if (p.count_work) add_work(w.hdr, kWorkSearch, work);
 }
 
+// Second window stage in lane form, over the points the first stage left open
+// (the list of k_collect): kOpenLanes lanes per open point, which split the rows
+// of the cells within K of its cell (outside the block within kprev that the
+// first stage searched) and then take the minimum of their bests.  Rows and
+// strip-dimension cells are clipped to the lane's best distance so far (float
+// bounds rounded outwards, so a clip only ever keeps extra cells).  The
+// candidate ranges of kOpenChunk rows are queued in LDS and tested as one
+// stream, two at a time.  A point stays open, listed for the ring search,
+// unless its best is strictly closer than the exterior of the block.
+constexpr int kOpenLanes = 4;                // lanes per open point (a power of two)
+constexpr int kOpenChunk = 5;                // rows per queue fill
+constexpr int kOpenQueue = 2 * kOpenChunk;   // two pieces per row at most
+#ifndef DPC_OPEN_CAP
+#define DPC_OPEN_CAP 256
+#endif
+constexpr uint32_t kOpenCap = DPC_OPEN_CAP;  // candidates per lane before the point goes to the ring search
+constexpr uint32_t kRingFromFirst = 1u << 31;  // ring-list flag: start from the first stage's block
+
+template <int D, int MODE>
+__device__ __forceinline__ void search_open(Blk blk, const Plan &p, const Ws &w, int K, int kprev) {
+  constexpr int W = (D + 1) / 2;
+  constexpr int RA = D > 1 ? D - 1 : 1;
+  if (grid_skipped(w.hdr)) return;
+  __shared__ uint2 queue_all[kOpenQueue * kBlock];  // each lane's queue of candidate ranges
+  uint2 *queue = queue_all + threadIdx.x;
+  const uint32_t nopen = uniform(as_const(&w.hdr->n_unres)[0]);
+  const int nr = p.gm - 1;
+  const int32_t L = p.L, nc = p.nc;
+  const int side = 2 * K + 1;
+  const int nrow = int(window_rows(p, K));
+  const int nchunk = (nrow + kOpenChunk - 1) / kOpenChunk;
+  const float inv_l = 1.0f / float(L), inv_side = 1.0f / float(side);
+  const uint4 *srec = w.srec;
+  const int sub = int(threadIdx.x) & (kOpenLanes - 1);
+  uint64_t work = 0;  // the lane's candidate tests (profiling)
+  // Every lane of a point's group runs the same iterations (the shuffles below).
+  const int64_t ngroups = grid_threads(blk) / kOpenLanes;
+  for (int64_t i = thread_index(blk) / kOpenLanes; i < int64_t(nopen); i += ngroups) {
+    const uint32_t q = w.unres[i];
+    LaneGeom<D> geo;
+    lane_geom<D>(p, w.spts + int64_t(q) * D, geo);
+    const uint64_t Ki = w.sK[q];
+    uint32_t qk[W];
+    if (MODE == kModeP16) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) qk[k] = w.spk[int64_t(q) * W + k];
+    }
+    uint64_t best = w.best[q];  // (D2 << kIdBits) | id, kNoKey if none
+    // candidate j's key, or kNoKey when it does not rank above the point
+    auto key_of = [&](uint32_t j) -> uint64_t {
+      uint64_t kj, d2;
+      if constexpr (MODE == kModeP16) {
+        uint32_t cw[W];
+        if (W <= 2 && srec) {  // words and rank key in one load
+          const uint4 rec = srec[j];
+          cw[0] = rec.x;
+          cw[W - 1] = W == 2 ? rec.y : rec.x;
+          kj = (uint64_t(rec.w) << 32) | rec.z;
+        } else {
+          kj = w.sK[j];
+          load_words<W>(w.spk + int64_t(j) * W, cw);
+        }
+        int32_t a = dot2_self_v(pk_sub16(qk[0], cw[0]), 0);
+#pragma unroll
+        for (int k = 1; k < W; ++k) a = dot2_self_v(pk_sub16(qk[k], cw[k]), a);
+        d2 = uint32_t(a);
+      } else {
+        kj = w.sK[j];
+        int32_t y[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) y[k] = w.spts[int64_t(j) * D + k];
+        d2 = exact_d2_u<D>(geo.x, y);
+      }
+      return kj > Ki ? (d2 << kIdBits) | uint32_t(~uint32_t(kj)) : kNoKey;
+    };
+    const int32_t xs = geo.xs, cs = geo.cs;
+    // the queued ranges' candidates, two per step (the next queued range is read
+    // one refill ahead)
+    uint32_t spent = 0;  // the lane's candidates so far
+    bool over = false;   // the lane gave up: past kOpenCap candidates
+    auto stream = [&](const uint32_t *pb, const uint32_t *pe) {
+      uint32_t m = 0, total = 0;
+#pragma unroll
+      for (int k = 0; k < kOpenQueue; ++k) {
+        if (pb[k] < pe[k]) {
+          queue[m * kBlock] = make_uint2(pb[k], pe[k]);
+          ++m;
+          total += pe[k] - pb[k];
+        }
+      }
+      // A dense neighbourhood would hold the whole wave back: the point goes to
+      // the ring search (a wave per point) instead.
+      over = over || spent + total > kOpenCap;
+      if (over) return;
+      spent += total;
+      // two candidates per step; the next queued range is read one refill ahead
+      uint32_t j = 0, e = 0, k = 1;
+      uint2 nx = make_uint2(0u, 0u);
+      if (m > 0) nx = queue[0];
+      for (uint32_t t = 0; t < total; t += 2) {
+        if (j == e) {
+          j = nx.x;
+          e = nx.y;
+          if (k < m) nx = queue[k * kBlock];
+          ++k;
+        }
+        const uint32_t j0 = j++;
+        const bool two = t + 1 < total;
+        if (two && j == e) {
+          j = nx.x;
+          e = nx.y;
+          if (k < m) nx = queue[k * kBlock];
+          ++k;
+        }
+        const uint32_t j1 = two ? j : j0;
+        j += two ? 1u : 0u;
+        const uint64_t k0 = key_of(j0), k1 = key_of(j1);
+        best = k0 < best ? k0 : best;
+        best = (two && k1 < best) ? k1 : best;
+      }
+      work += total;
+    };
+    if (side <= kOpenChunk && nr >= 1) {
+      // A chunk is one line of the window: the rows of every value of the first
+      // row digit, whose gaps, cells and flags are set once per point; the other
+      // digits' share is set once per line.  A strip-dimension cell is kept when
+      // its gap and the row's, squared and summed, can be within the best (float
+      // bounds rounded outwards); no square root.
+      constexpr int kHalf = kOpenChunk / 2;
+      float g0[kOpenChunk], gl[kHalf + 1], gr[kHalf + 1];
+      int32_t nb0s[kOpenChunk];
+      bool ok0[kOpenChunk], in0[kOpenChunk], okl[kHalf + 1], okr[kHalf + 1];
+      int32_t stride0 = 1;
+      for (int t = 1; t < nr; ++t) stride0 *= nc;
+#pragma unroll
+      for (int c = 0; c < kOpenChunk; ++c) {
+        const int32_t o = c - K;
+        const int32_t nb = geo.c[0] + o;
+        ok0[c] = c < side && nb >= 0 && nb < nc;
+        in0[c] = o <= kprev && o >= -kprev;
+        const float a0 = float(cell_gap32(geo.x[0], nb, L));
+        g0[c] = a0 * a0;
+        nb0s[c] = nb * stride0;
+      }
+      // strip cells cs - u and cs + u (u <= K), squared gaps lowered a little
+#pragma unroll
+      for (int u = 1; u <= kHalf; ++u) {
+        okl[u] = u <= K && cs - u >= 0;
+        okr[u] = u <= K && cs + u < nc;
+        const float al = float(cell_gap32(xs, cs - u, L)), ar = float(cell_gap32(xs, cs + u, L));
+        gl[u] = al * al * (1.0f - 0x1p-20f);
+        gr[u] = ar * ar * (1.0f - 0x1p-20f);
+      }
+      const int nlines = nrow / side;
+      for (int ln = sub; ln < nlines; ln += kOpenLanes) {
+        float part = 0.0f;
+        int32_t rk = 0;
+        bool ok12 = true, in12 = kprev >= 0;
+        {
+          int32_t r = ln;  // the other digits, the second fastest first
+#pragma unroll
+          for (int t = 1; t < RA; ++t) {
+            if (t < nr) {
+              const int32_t qd = int32_t((float(r) + 0.5f) * inv_side);  // exact: r < 2^20
+              const int32_t o = r - qd * side - K;
+              r = qd;
+              const int32_t nb = geo.c[t] + o;
+              ok12 = ok12 && nb >= 0 && nb < nc;
+              in12 = in12 && o <= kprev && o >= -kprev;
+              rk = rk * nc + nb;
+              const float gp = float(cell_gap32(geo.x[t], nb, L));
+              part = __builtin_fmaf(gp, gp, part);
+            }
+          }
+        }
+        const bool clip = best != kNoKey;
+        const float bf = clip ? float(best >> kIdBits) * (1.0f + 0x1p-20f) + 1.0f : 0.0f;
+        uint32_t pb[kOpenQueue], pe[kOpenQueue];
+#pragma unroll
+        for (int c = 0; c < kOpenChunk; ++c) {
+          pb[2 * c] = pe[2 * c] = pb[2 * c + 1] = pe[2 * c + 1] = 0;
+          const float mdf = (part + g0[c]) * (1.0f - 0x1p-20f);
+          if (ok12 && ok0[c] && (!clip || mdf <= bf)) {
+            // strip cells cs + lo .. cs + hi: the gaps grow away from cs
+            int32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int u = 1; u <= kHalf; ++u) {
+              if (okl[u] && (!clip || gl[u] + mdf <= bf)) lo = -u;
+              if (okr[u] && (!clip || gr[u] + mdf <= bf)) hi = u;
+            }
+            const int32_t base = nb0s[c] + rk;  // row index
+            const int32_t row0 = base * nc + cs;
+            if (ok12 && in12 && in0[c]) {  // two pieces: left and right of the first block
+              if (lo <= -kprev - 1) {
+                pb[2 * c] = w.cnt[row0 + lo];
+                pe[2 * c] = w.cnt[row0 - kprev];
+              }
+              if (hi >= kprev + 1) {
+                pb[2 * c + 1] = w.cnt[row0 + kprev + 1];
+                pe[2 * c + 1] = w.cnt[row0 + hi + 1];
+              }
+            } else {
+              pb[2 * c] = w.cnt[row0 + lo];
+              pe[2 * c] = w.cnt[row0 + hi + 1];
+            }
+          }
+        }
+        stream(pb, pe);
+      }
+    } else {
+      for (int ch = sub; ch < nchunk; ch += kOpenLanes) {
+        // digits of the chunk's first row (each in [0, 2K], the first fastest)
+        // (r / side in float: exact, as r < 2^20 keeps the rounding far below the
+        // 1 / (2 side) that (r + 1/2) / side keeps from an integer)
+        int32_t dg[RA];
+        {
+          int32_t r = ch * kOpenChunk;
+#pragma unroll
+          for (int t = 0; t < RA; ++t) {
+            dg[t] = 0;
+            if (t < nr) {
+              const int32_t qd = int32_t((float(r) + 0.5f) * inv_side);
+              dg[t] = r - qd * side;
+              r = qd;
+            }
+          }
+        }
+        const uint64_t bestd2 = best >> kIdBits;
+        const bool clip = best != kNoKey;
+        const float bf = clip ? float(bestd2) * (1.0f + 0x1p-20f) + 1.0f : 0.0f;
+        uint32_t pb[kOpenQueue], pe[kOpenQueue];
+#pragma unroll
+        for (int c = 0; c < kOpenChunk; ++c) {
+          pb[2 * c] = pe[2 * c] = pb[2 * c + 1] = pe[2 * c + 1] = 0;
+          if (ch * kOpenChunk + c < nrow) {
+            int32_t rowk = 0;
+            float mdf = 0.0f;
+            bool ok = true, inner = kprev >= 0;
+#pragma unroll
+            for (int t = 0; t < RA; ++t) {
+              if (t < nr) {
+                const int32_t o = dg[t] - K;
+                const int32_t nb = geo.c[t] + o;
+                ok = ok && nb >= 0 && nb < nc;
+                inner = inner && o <= kprev && o >= -kprev;
+                rowk = rowk * nc + nb;
+                const float gp = float(cell_gap32(geo.x[t], nb, L));
+                mdf = __builtin_fmaf(gp, gp, mdf);
+              }
+            }
+            mdf *= 1.0f - 0x1p-20f;
+            if (ok && (!clip || mdf <= bf)) {
+              int32_t lo = max(cs - K, 0), hi = min(cs + K, nc - 1);
+              if (clip) {
+                const float rr = sqrt_approx(bf - mdf) * (1.0f + 0x1p-20f) + 1.0f;
+                const float xa = float(xs) - rr, xz = float(xs) + rr;
+                if (xa > 0.0f) lo = max(lo, int32_t(xa * inv_l * (1.0f - 0x1p-20f)));
+                if (xz < float(DPC_COORD_LIMIT)) hi = min(hi, int32_t(xz * inv_l * (1.0f + 0x1p-20f)));
+              }
+              const int32_t base = rowk * nc;
+              const int32_t l_hi = inner ? min(hi, cs - kprev - 1) : hi;
+              const int32_t r_lo = inner ? max(lo, cs + kprev + 1) : hi + 1;
+              if (lo <= l_hi) {
+                pb[2 * c] = w.cnt[base + lo];
+                pe[2 * c] = w.cnt[base + l_hi + 1];
+              }
+              if (r_lo <= hi) {
+                pb[2 * c + 1] = w.cnt[base + r_lo];
+                pe[2 * c + 1] = w.cnt[base + hi + 1];
+              }
+            }
+          }
+          bool carry = true;  // the next row
+#pragma unroll
+          for (int t = 0; t < RA; ++t) {
+            if (t < nr && carry) {
+              carry = dg[t] == 2 * K;
+              dg[t] = carry ? 0 : dg[t] + 1;
+            }
+          }
+        }
+        stream(pb, pe);
+      }
+    }
+    // the group's best, and whether a lane gave up
+    uint32_t gave_up = over ? 1u : 0u;
+#pragma unroll
+    for (int off = 1; off < kOpenLanes; off <<= 1) {
+      const uint64_t o = __shfl_xor(best, off, kWave);
+      best = o < best ? o : best;
+      gave_up |= uint32_t(__shfl_xor(int(gave_up), off, kWave));
+    }
+    if (sub == 0) {
+      // A point whose block was not searched whole keeps its best (a bound from
+      // real candidates) and is listed with kRingFromFirst: the ring search then
+      // grows from the first stage's block.
+      const uint64_t ext = lane_exterior_d2<D>(p, geo, K);
+      const bool resolved = !gave_up && (ext == kNoKey || (best != kNoKey && (best >> kIdBits) < ext));
+      w.best[q] = best;
+      if (!resolved) w.slot[wave_append(&w.hdr->n_ring, true)] = q | (gave_up ? kRingFromFirst : 0u);
+    }
+  }
+  if (p.count_work) add_work(w.hdr, kWorkSearch, work);
+}
+
 // One search stage.  Each wave takes `group` consecutive tasks, gathers their
 // open points (all points in the first stage) into batches of 64 per strip
 // through an LDS queue, and searches each batch's window of radius K.
@@ -395,34 +700,6 @@ struct SegLds {
   uint2 seg[kWave][2 * kRingRows];    // each lane's row pieces: {first position, count}
 };
 
-// A bound r >= sqrt(v) (v < 2^40) from the float square root: the conversion and
-// the root are each within a relative 2^-23 of exact, so a 2^-20 margin and one
-// unit cover them.
-__device__ __forceinline__ int32_t sqrt_ceil_bound(uint64_t v) {
-  const float f = __builtin_sqrtf(float(v));
-  return int32_t(f * (1.0f + 0x1p-20f)) + 1;
-}
-
-// Gap from coordinate x to cell cc (side L) along one dimension, 32-bit.
-__device__ __forceinline__ uint32_t cell_gap32(int32_t x, int32_t cc, int32_t L) {
-  const int32_t lo = cc * L, hi = lo + L - 1;
-  return uint32_t(x < lo ? lo - x : (x > hi ? x - hi : 0));
-}
-
-// Exact squared distance: each |dx| < 2^31, its square formed as a 32 x 32 -> 64
-// bit product.
-template <int D>
-__device__ __forceinline__ uint64_t exact_d2_u(const int32_t *a, const int32_t *b) {
-  uint64_t s = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    const int32_t df = a[k] - b[k];
-    const uint32_t ad = uint32_t(df < 0 ? -df : df);
-    s += uint64_t(ad) * uint64_t(ad);
-  }
-  return s;
-}
-
 template <int D>
 __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, int k_start) {
   __shared__ SegLds lds_all[kWavesPerBlock];
@@ -430,10 +707,12 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
   constexpr int RA = D > 1 ? D - 1 : 1;
   const int lane = lane_id();
   if (grid_skipped(w.hdr)) return;
-  const uint32_t nunres = uniform(as_const(&w.hdr->n_unres)[0]);
+  // the open-point stage's list when it ran, else the first stage's
+  const uint32_t nunres = uniform(as_const(p.openK ? &w.hdr->n_ring : &w.hdr->n_unres)[0]);
+  if (p.openK) k_start = p.openK;
   DPC_CONST(int32_t) *spc = as_const(w.spts);
   DPC_CONST(uint64_t) *sKc = as_const(w.sK);
-  DPC_CONST(uint32_t) *unres = as_const(w.unres);
+  DPC_CONST(uint32_t) *unres = as_const(p.openK ? w.slot : w.unres);
   DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
   const int32_t L = p.L, nc = p.nc;
   const int nr = p.gm - 1;  // row dimensions
@@ -441,7 +720,8 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
   uint64_t work = 0;  // candidate tests (wave-uniform; profiling)
   const uint32_t nw = grid_waves(blk);
   for (uint32_t u = wave_index(blk); u < nunres; u += nw) {
-    const uint32_t q = uniform(unres[u]);
+    const uint32_t entry = uniform(unres[u]);
+    const uint32_t q = entry & ~kRingFromFirst;
     int32_t x[D], c[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -457,7 +737,8 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
     const int64_t budget = min(int64_t(prefix / kWave) + 2, int64_t(p.ring_cap));
     int64_t cost = 0;
     bool defer = false;
-    int32_t k0 = k_start;  // -1: nothing searched yet
+    // -1: nothing searched yet
+    int32_t k0 = (entry & kRingFromFirst) ? (p.stageK[0] == 0 ? -1 : p.stageK[0]) : k_start;
 
     for (;;) {
       // This pass: the cells of the box [lo, lo + ext) (row dimensions) x [sa, sb]
@@ -477,69 +758,92 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
         }
       };
       int32_t lo[RA], ext[RA];
-      uint32_t mg[RA];  // ceil(2^32 / ext): r / ext as a high product while r * ext < 2^32
       uint64_t nrows = 1;
-      int32_t emax = 1;
 #pragma unroll
       for (int t = 0; t < RA; ++t) {
         lo[t] = 0;
         ext[t] = 1;
-        mg[t] = 0;
         if (t < nr) {
           int32_t a, b;
           box(x[t], c[t], &a, &b);
           lo[t] = a;
           ext[t] = b - a + 1;
-          mg[t] = ext[t] > 1 ? 0xFFFFFFFFu / uint32_t(ext[t]) + 1u : 0u;
           nrows *= uint64_t(ext[t]);
-          emax = max(emax, ext[t]);
         }
       }
       int32_t sa, sb;
       box(xs, cl, &sa, &sb);
-      const bool fast_div = nrows * uint64_t(emax) < (uint64_t(1) << 32);
-      for (uint64_t r0b = 0; r0b < nrows; r0b += uint64_t(kWave) * kRingRows) {
+      // A pass costs at least kRingRows per round: one that cannot end within the
+      // budget defers the point at once.
+      constexpr uint32_t kStride = kWave * kRingRows;  // rows per round
+      if (cost + int64_t(kRingRows) * int64_t((nrows + kStride - 1) / kStride) >= budget) {
+        defer = true;
+        break;
+      }
+      // Rows are visited as mixed-radix numbers (digit t in [0, ext[t])): each lane
+      // keeps the digits of its kRingRows rows and adds the round stride to them
+      // with carries.  nrows < 2^26 here (the budget is at most 2^20).
+      uint32_t sd[RA], dd[kRingRows][RA], rl[kRingRows];
+      {
+        // r / e as a high product with m = ceil(2^32 / e): exact while r * e < 2^32
+        // (here r < kStride and e <= nc < 2^18)
+        uint32_t m[RA];
+#pragma unroll
+        for (int t = 0; t < RA; ++t) m[t] = ext[t] > 1 ? 0xFFFFFFFFu / uint32_t(ext[t]) + 1u : 0u;
+        auto digits = [&](uint32_t r, uint32_t *dg) {
+#pragma unroll
+          for (int t = 0; t < RA; ++t) {
+            const uint32_t q = ext[t] > 1 ? __umulhi(r, m[t]) : r;
+            dg[t] = r - q * uint32_t(ext[t]);
+            r = q;
+          }
+        };
+        digits(kStride, sd);
+#pragma unroll
+        for (int i = 0; i < kRingRows; ++i) {
+          rl[i] = uint32_t(i * kWave + lane);
+          digits(rl[i], dd[i]);
+        }
+      }
+      const float inv_l = 1.0f / float(L);
+      for (uint32_t r0b = 0; r0b < uint32_t(nrows); r0b += kStride) {
         const uint64_t bestd2 = best >> kIdBits;  // huge when there is no best yet
+        // the best distance as a float a little above it (no clipping without one)
+        const bool clip = bestd2 < (uint64_t(1) << 40);
+        const float bf = clip ? float(bestd2) * (1.0f + 0x1p-20f) + 1.0f : 0.0f;
         uint2 sg[2 * kRingRows];
         uint32_t mine = 0;  // this lane's candidates in the round
 #pragma unroll
         for (int i = 0; i < kRingRows; ++i) {
           sg[2 * i] = make_uint2(0u, 0u);
           sg[2 * i + 1] = make_uint2(0u, 0u);
-          const uint64_t r0 = r0b + uint64_t(i) * kWave + uint64_t(lane);
-          if (r0 < nrows) {
-            uint64_t md = 0;
+          if (rl[i] < uint32_t(nrows)) {
+            float mdf = 0.0f;  // squared gap of the row, a little below the exact value
             int32_t rowk = 0;  // row index of the cell table (ncells < 2^31)
             bool outer = k0 < 0;
-            uint32_t r32 = uint32_t(r0);
-            uint64_t r64 = r0;
 #pragma unroll
             for (int t = 0; t < RA; ++t) {
               if (t < nr) {
-                int32_t d;
-                if (fast_div) {
-                  const uint32_t qd = ext[t] > 1 ? __umulhi(r32, mg[t]) : r32;
-                  d = int32_t(r32 - qd * uint32_t(ext[t]));
-                  r32 = qd;
-                } else {
-                  d = int32_t(r64 % uint64_t(ext[t]));
-                  r64 /= uint64_t(ext[t]);
-                }
-                const int32_t nb = lo[t] + d;
+                const int32_t nb = lo[t] + int32_t(dd[i][t]);
                 const int32_t o = nb - c[t];
                 outer = outer || o > k0 || o < -k0;
                 rowk = rowk * nc + nb;
-                const uint32_t gp = cell_gap32(x[t], nb, L);
-                md += uint64_t(gp) * uint64_t(gp);
+                const float gp = float(cell_gap32(x[t], nb, L));  // exact: below 2^24
+                mdf = __builtin_fmaf(gp, gp, mdf);
               }
             }
-            if (md <= bestd2) {
-              // strip-dimension cells that can hold a point within the best distance
+            mdf *= 1.0f - 0x1p-20f;
+            // A row is skipped only when it is surely farther than the best.
+            if (!clip || mdf <= bf) {
+              // strip-dimension cells that can hold a point within the best distance:
+              // a bound above sqrt(best - gap^2), and cell indices rounded outwards
               int32_t lo_s = sa, hi_s = sb;
-              if (bestd2 < (uint64_t(1) << 40)) {
-                const int32_t rr = sqrt_ceil_bound(bestd2 - md);
-                lo_s = max(lo_s, max(xs - rr, 0) / L);
-                hi_s = min(hi_s, min(xs + rr, DPC_COORD_LIMIT - 1) / L);
+              if (clip) {
+                // the hardware root (within a few ulp; the margin is 8 ulp)
+                const float rr = sqrt_approx(bf - mdf) * (1.0f + 0x1p-20f) + 1.0f;
+                const float xa = float(xs) - rr, xz = float(xs) + rr;
+                if (xa > 0.0f) lo_s = max(lo_s, int32_t(xa * inv_l * (1.0f - 0x1p-20f)));
+                if (xz < float(DPC_COORD_LIMIT)) hi_s = min(hi_s, int32_t(xz * inv_l * (1.0f + 0x1p-20f)));
               }
               const int32_t base = rowk * nc;
               if (outer) {  // the whole row lies outside the block searched so far
@@ -560,6 +864,15 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
               }
             }
           }
+          // the lane's row in the next round
+          uint32_t carry = 0;
+#pragma unroll
+          for (int t = 0; t < RA; ++t) {
+            const uint32_t v = dd[i][t] + sd[t] + carry;
+            carry = v >= uint32_t(ext[t]) ? 1u : 0u;
+            dd[i][t] = carry ? v - uint32_t(ext[t]) : v;
+          }
+          rl[i] += kStride;
         }
 #pragma unroll
         for (int i = 0; i < 2 * kRingRows; ++i) mine += sg[i].y;
@@ -783,6 +1096,10 @@ __global__ __launch_bounds__(kBlock) DPC_WAVES(DPC_SEARCH_WAVES) void k_search_l
   search_lanes<D, MODE>(xcd_blk(), p, w, K);
 }
 __global__ __launch_bounds__(kBlock) void k_collect(Plan p, Ws w) { collect_body(grid_blk(), p, w.flag, w.unres, w.hdr); }
+template <int D, int MODE>
+__global__ __launch_bounds__(kBlock) void k_search_open(Plan p, Ws w) {
+  search_open<D, MODE>(grid_blk(), p, w, p.openK, p.stageK[0]);
+}
 template <int D>
 __global__ __launch_bounds__(kBlock) DPC_WAVES(DPC_RING_WAVES) void k_ringk(Plan p, Ws w, int k_start) {
   ringk_body<D>(grid_blk(), p, w, k_start);
@@ -833,6 +1150,18 @@ __global__ __launch_bounds__(kBlock) void kb_collect(const JobDev *jobs, VMap m)
 }
 
 template <int D>
+__global__ __launch_bounds__(kBlock) void kb_search_open(const JobDev *jobs, VMap m) {
+  DPC_FOR_VBLOCKS(m)
+  if (p.openK) {
+    if (p.openMode == kModeP16)
+      search_open<D, kModeP16>(k, p, w, p.openK, p.stageK[0]);
+    else
+      search_open<D, kModeI64>(k, p, w, p.openK, p.stageK[0]);
+  }
+}
+}
+
+template <int D>
 __global__ __launch_bounds__(kBlock) void kb_ringk(const JobDev *jobs, VMap m) {
   DPC_FOR_VBLOCKS(m)
   const int kl = uniform(int32_t(as_const(jobs)[j].p.stageK[p.nstages - 1]));
@@ -879,6 +1208,17 @@ hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta,
   {
     ProfScope ps(s, kProfRingK);
     DPC_LAUNCH((k_collect), blocks_for(p.n, kBlock * kCollectPer), kBlock, s, p, w);
+  }
+  if (p.openK) {  // kOpenLanes lanes per open point: up to 16 points each if all were open
+    ProfScope ps(s, kProfOpen);
+    const unsigned ob = blocks_for(p.n, kBlock * 16 / kOpenLanes);
+    if (p.openMode == kModeP16)
+      DPC_LAUNCH((k_search_open<D, kModeP16>), ob, kBlock, s, p, w);
+    else
+      DPC_LAUNCH((k_search_open<D, kModeI64>), ob, kBlock, s, p, w);
+  }
+  {
+    ProfScope ps(s, kProfRingK);
     const int kl = p.stageK[p.nstages - 1];
     DPC_LAUNCH((k_ringk<D>), rb, kBlock, s, p, w, kl == 0 ? -1 : kl);  // after a ball stage: nothing
   }
@@ -914,6 +1254,9 @@ template <int DD>
 void batch_dep_group(const BatchMaps &B, const VMap &m, int what, int st, hipStream_t s) {
   if (what == 0) {
     DPC_LAUNCH((kb_search<DD>), vgrid(m), kBlock, s, B.jobs, m, st);
+  } else if (what == 2) {
+    ProfScope ps(s, kProfOpen);
+    DPC_LAUNCH((kb_search_open<DD>), vgrid(m), kBlock, s, B.jobs, m);
   } else {
     {
       ProfScope ps(s, kProfRingK);
@@ -956,6 +1299,7 @@ hipError_t batch_dependent(const BatchMaps &B, hipStream_t s) {
     ProfScope ps(s, kProfRingK);
     if (vgrid(B.pts)) DPC_LAUNCH((kb_collect), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   }
+  if (B.any_open && (e = batch_groups(B, 2, 0, s)) != hipSuccess) return e;
   if ((e = batch_groups(B, 1, 0, s)) != hipSuccess) return e;
   ProfScope ps(s, kProfFinish);
   if (vgrid(B.pts)) DPC_LAUNCH((kb_finish), vgrid(B.pts), kBlock, s, B.jobs, B.pts);

@@ -361,6 +361,7 @@ __device__ __forceinline__ void reset_hdr(DevHeader *hdr, int grid) {
     }
     hdr->n_unres = 0;
     hdr->n_peaks = 0;
+    hdr->n_ring = 0;
   }
 }
 

@@ -12,6 +12,7 @@ enum ProfKernel : int {
   kProfRankKeys,
   kProfRankSort,
   kProfSearch,
+  kProfOpen,       // the second window stage over the open points (lane form)
   kProfRingK,
   kProfPeaks,
   kProfFinish,

@@ -178,6 +178,8 @@ template <int D>
 struct LaneGeom {
   int32_t x[D];  // the query's coordinates
   int32_t c[D];  // its cell coordinates (first gm used)
+  int32_t xs;    // the coordinate along the strip dimension (gm - 1), and its cell
+  int32_t cs;
 };
 
 template <int D>
@@ -194,6 +196,10 @@ __device__ __forceinline__ void lane_geom(const Plan &p, const int32_t *src, Lan
   }
 #pragma unroll
   for (int t = 0; t < D; ++t) g.c[t] = t < p.gm ? g.x[t] / p.L : 0;
+  // read again from memory: indexing x by the run-time gm would move the
+  // register arrays to scratch memory
+  g.xs = src[p.gm - 1];
+  g.cs = g.xs / p.L;
 }
 
 // Row offsets of a window of radius K, as an odometer over the first gm - 1
@@ -240,16 +246,6 @@ struct RowWalk {
   }
 };
 
-// A[s] for a run-time s < D without indexing a register array by a run-time
-// value (which would move the array to memory): D selects.
-template <int D>
-__device__ __forceinline__ int32_t pick(const int32_t *a, int s) {
-  int32_t v = a[0];
-#pragma unroll
-  for (int t = 1; t < D; ++t) v = t == s ? a[t] : v;
-  return v;
-}
-
 // Gap from coordinate x to cell cc along a grid dimension (0 inside the cell).
 __device__ __forceinline__ int64_t cell_gap(int32_t x, int32_t cc, int32_t L) {
   const int64_t lo = int64_t(cc) * L, hi = lo + L - 1;
@@ -276,7 +272,7 @@ __device__ __forceinline__ bool lane_row(const Plan &p, const LaneGeom<D> &g, co
   }
   if (!ok || dy2 > clip) return false;
   const int s = p.gm - 1;
-  const int32_t xs = pick<D>(g.x, s), cs = pick<D>(g.c, s);
+  const int32_t xs = g.xs, cs = g.cs;
   int32_t lo = cs - K, hi = cs + K;
   while (lo < cs) {
     const int64_t gp = cell_gap(xs, lo, p.L);
@@ -304,6 +300,45 @@ __device__ __forceinline__ bool lane_row(const Plan &p, const LaneGeom<D> &g, co
     *e = start[rowk * p.nc + hi + 1];
   }
   return *b < *e;
+}
+
+// Square root of a float >= 0 by the hardware instruction (not correctly
+// rounded; callers add a margin).
+__device__ __forceinline__ float sqrt_approx(float v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_sqrtf(v);
+#else
+  return __builtin_sqrtf(v);
+#endif
+}
+
+// A bound r >= sqrt(v) (v < 2^40) from the float square root: the conversion and
+// the root are each within a relative 2^-23 of exact, so a 2^-20 margin and one
+// unit cover them.
+__device__ __forceinline__ int32_t sqrt_ceil_bound(uint64_t v) {
+  const float f = __builtin_sqrtf(float(v));
+  return int32_t(f * (1.0f + 0x1p-20f)) + 1;
+}
+
+// Gap from coordinate x to cell cc (side L) along one dimension, 32-bit and
+// branch-free (at most one of the two differences is positive).
+__device__ __forceinline__ uint32_t cell_gap32(int32_t x, int32_t cc, int32_t L) {
+  const int32_t lo = cc * L, hi = lo + L - 1;
+  return uint32_t(max(max(lo - x, x - hi), 0));
+}
+
+// Exact squared distance: each |dx| < 2^31, its square formed as a 32 x 32 -> 64
+// bit product.
+template <int D>
+__device__ __forceinline__ uint64_t exact_d2_u(const int32_t *a, const int32_t *b) {
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int32_t df = a[k] - b[k];
+    const uint32_t ad = uint32_t(df < 0 ? -df : df);
+    s += uint64_t(ad) * uint64_t(ad);
+  }
+  return s;
 }
 
 constexpr int ipow3(int e) { return e <= 0 ? 1 : 3 * ipow3(e - 1); }

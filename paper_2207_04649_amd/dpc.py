@@ -33,7 +33,7 @@ class DpcError(RuntimeError):
 class PlanInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "R", "cell_side", "cells_per_dim", "cells", "strip_cells", "strips", "max_tasks", "mode",
-        "workspace_bytes", "window_radius", "stages", "grid_dims", "lanes")]
+        "workspace_bytes", "window_radius", "stages", "grid_dims", "lanes", "open_radius")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -43,13 +43,14 @@ class Tuning(ctypes.Structure):
     """dpc_tuning: plan options of one problem (0 = default)."""
     _fields_ = [("subdiv", ctypes.c_int32), ("strip_cells", ctypes.c_int32), ("nstages", ctypes.c_int32),
                 ("stage_radius", ctypes.c_int32 * 4), ("stage_group", ctypes.c_int32 * 4),
-                ("ring_cap", ctypes.c_int32), ("grid_dims", ctypes.c_int32), ("lanes", ctypes.c_int32)]
+                ("ring_cap", ctypes.c_int32), ("grid_dims", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("open_radius", ctypes.c_int32)]
 
     @classmethod
-    def make(cls, subdiv=0, strip_cells=0, stages=(), ring_cap=0, grid_dims=0, lanes=0) -> "Tuning":
+    def make(cls, subdiv=0, strip_cells=0, stages=(), ring_cap=0, grid_dims=0, lanes=0, open_radius=0) -> "Tuning":
         t = cls()
         t.subdiv, t.strip_cells, t.ring_cap = int(subdiv), int(strip_cells), int(ring_cap)
-        t.grid_dims, t.lanes = int(grid_dims), int(lanes)
+        t.grid_dims, t.lanes, t.open_radius = int(grid_dims), int(lanes), int(open_radius)
         t.nstages = len(stages)
         for k, (radius, group) in enumerate(stages):
             t.stage_radius[k], t.stage_group[k] = int(radius), int(group)
@@ -57,7 +58,7 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {"subdiv": self.subdiv, "strip_cells": self.strip_cells, "ring_cap": self.ring_cap,
-                "grid_dims": self.grid_dims, "lanes": self.lanes,
+                "grid_dims": self.grid_dims, "lanes": self.lanes, "open_radius": self.open_radius,
                 "stages": [(self.stage_radius[k], self.stage_group[k]) for k in range(self.nstages)]}
 
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2207_04649_amd", "csrc")
 
 
-def build(out_dir: str, asan: bool = False) -> str:
+def build(out_dir: str, asan: bool = False, defines: tuple = ()) -> str:
     os.makedirs(out_dir, exist_ok=True)
     exe = os.path.join(out_dir, "dpc_emu_asan" if asan else "dpc_emu")
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
@@ -20,6 +20,6 @@ def build(out_dir: str, asan: bool = False) -> str:
         cmd[1:1] = ["-fsanitize=address", "-fno-omit-frame-pointer"]
     # extra -D options of the kernel sources (space-separated), e.g. to check a
     # compile-time variant of a kernel
-    cmd[1:1] = os.environ.get("DPC_EMU_DEFINES", "").split()
+    cmd[1:1] = list(defines) + os.environ.get("DPC_EMU_DEFINES", "").split()
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     return exe

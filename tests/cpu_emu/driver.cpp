@@ -8,7 +8,7 @@
 // jobs run through dpc_batch_run and the output holds one record per job
 // (the status fields are those of the batch calls).  --tuning SPEC (batch only)
 // gives every job the plan options of SPEC, "key=value" items separated by ';':
-// subdiv, strip, ring, gm, lanes, and stages=K:group,K:group,...
+// subdiv, strip, ring, gm, lanes, open, and stages=K:group,K:group,...
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -82,6 +82,7 @@ bool parse_tuning(const std::string &spec, dpc_tuning *t) {
     else if (k == "ring") t->ring_cap = x;
     else if (k == "gm") t->grid_dims = x;
     else if (k == "lanes") t->lanes = x;
+    else if (k == "open") t->open_radius = x;
     else return false;
   }
   return true;

@@ -121,6 +121,22 @@ def test_emulated_batch_matches_oracle(emu_exe):
         pins.assert_same(got, pins.run(scan, *job), keys=("rho", "dep", "delta", "label", "ncenters"), ctx=f"job {k}")
 
 
+def test_emulated_open_stage_hand_over_matches_oracle():
+    """The lane form's open-point stage gives a point up to the ring search once a
+    lane passes its candidate cap; with a cap of two candidates nearly every open
+    point is handed over, and the results still equal the oracle's."""
+    exe = build_emu.build(os.path.join(ROOT, "_build", "emu_cap"), asan=True, defines=("-DDPC_OPEN_CAP=2",))
+    jobs = []
+    for k, (n, d, dc) in enumerate([(400, 4, 12000.0), (300, 3, 9000.0), (200, 2, 4000.0)]):
+        pts = inputs.uniform_points(n, d, 131071, 700 + k)
+        pts[n // 2:] = pts[: n - n // 2] + (pts[: n - n // 2] % 7)
+        jobs.append((np.clip(pts, 0, 131071).astype(np.int32), dc, 2, dc * 1.5))
+    outs = run_emu_batch(exe, jobs, "lanes=2")
+    for k, (job, got) in enumerate(zip(jobs, outs)):
+        assert got["status"] == 0 and got["sync"] == 0, k
+        pins.assert_same(got, pins.run(scan, *job), keys=("rho", "dep", "delta", "label", "ncenters"), ctx=f"job {k}")
+
+
 @pytest.mark.parametrize("tuning", [
     "stages=0:1",                      # ball stage, ring search from nothing
     "stages=0:1,2:4;gm=2",             # ball then a gathered stage, partial grid
@@ -128,6 +144,8 @@ def test_emulated_batch_matches_oracle(emu_exe):
     "lanes=2",                         # one query per lane, every dimension
     "lanes=2;stages=2:1;gm=2",         # lane form, radius-2 stage, partial grid
     "lanes=2;subdiv=2;ring=3",
+    "lanes=2;open=-1",                 # lane form without the open-point stage
+    "lanes=2;open=3;ring=2",           # a radius-3 open-point stage, short rings
     "lanes=1",                         # tasks of 64 queries, every dimension
 ])
 def test_emulated_plan_options_match_oracle(emu_exe, tuning):
