@@ -151,8 +151,8 @@ typedef struct {
   int64_t stages;        /* dependent-search stages */
   int64_t grid_dims;     /* coordinates the cells index (the first grid_dims of d) */
   int64_t lanes;         /* kernel form: 0 tasks of 64 queries sharing windows, 1 one query per lane */
-  int64_t open_radius;   /* lane form: radius of the second window stage over the points the
-                            first leaves open (0: none) */
+  int64_t open_radius;   /* lane form: radius of the optional second window stage over the
+                            points the first leaves open (0: none) */
 } dpc_plan_info;
 dpc_status dpc_plan(int64_t n, int32_t d, double d_cut, dpc_plan_info *out);
 
@@ -183,7 +183,7 @@ typedef struct {
   int32_t stage_radius[4]; /* window radius of each stage in cells (1..64); 0: the density
                               window clipped to the cut-off ball (final when closer than d_cut).
                               Lane form runs only the first stage (a block of that radius,
-                              or the ball), then the open-point stage and the ring search */
+                              or the ball), then the ring search */
   int32_t stage_group[4];  /* tasks whose open points one wave gathers (1..64) */
   int32_t ring_cap;        /* most ring-search steps per point before the prefix scan */
   int32_t grid_dims;       /* coordinates the cells index (default d up to 4, else 3; d if
@@ -192,9 +192,9 @@ typedef struct {
                               (dense data); 2: one query per lane with its own window (sparse
                               data, where a strip holds a few points); 0: the default (lanes for
                               4-D points) */
-  int32_t open_radius;     /* lane form after a block stage of radius K: the second window stage,
-                              over the points the first leaves open, has this radius (K+1..16);
-                              0: 2K; -1: none (the ring search starts from the first block) */
+  int32_t open_radius;     /* lane form after a block stage of radius K: a second window stage of
+                              this radius (K+1..16) over the points the first leaves open, before
+                              the ring search; 0: none (the default) */
 } dpc_tuning;
 
 /* dpc_plan with explicit options (tuning may be NULL). */

@@ -23,6 +23,7 @@ CANDIDATES = [
     {"lanes": 2, "grid_dims": 8},          # one query per lane, every coordinate indexed
     {"lanes": 2, "stages": [(0, 1)]},      # one query per lane, the ball stage
     {"lanes": 2, "ring_cap": 384},
+    {"lanes": 2, "open_radius": 2},        # one query per lane, a second lane stage for open points
     {"subdiv": 1},
     {"subdiv": 2},
     {"subdiv": 3},

@@ -251,31 +251,27 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
     p.stageMode[p.nstages] = (gm == d && p16) ? kModeP16 : kModeI64;
     ++p.nstages;
   }
-  // Lane form: a second window stage, of twice the first's radius, over the
-  // points the first leaves open; the ring search grows from its block.
+  // Lane form, on request: a second window stage over the points the first
+  // leaves open; the ring search then grows from its block.  Off by default:
+  // on 4M 4-D random walks it took as long as the ring-search passes it saves
+  // (0.40 + 0.87 ms against 1.27 ms), and longer in the many-job form.
   p.openK = 0;
   p.openMode = kModeI64;
-  if (p.lanes && p.stageK[0] >= 1) {
-    int K2 = 2 * p.stageK[0];
+  {
     const int v = opt ? opt->open_radius : 0;
-    if (v < -1 || v > 16 || (v > 0 && v <= p.stageK[0])) return false;
-    if (v == -1) K2 = 0;
-    if (v > 0) K2 = v;
-    if (K2 > 16) K2 = 0;
-    int64_t rows = 1;  // the stage's rows stay below 2^20
-    for (int t = 0; t < gm - 1 && K2; ++t) rows *= 2 * K2 + 1;
-    if (rows > (int64_t(1) << 20)) {
-      if (v > 0) return false;
-      K2 = 0;
-    }
-    if (K2) {
-      p.openK = K2;
-      p.openMode = (gm == d && (int64_t(K2) + 1) * L <= E) ? kModeP16 : kModeI64;
+    if (v < 0 || v > 16) return false;
+    if (v > 0) {
+      if (!p.lanes || p.stageK[0] < 1 || v <= p.stageK[0]) return false;
+      int64_t rows = 1;  // the stage's rows stay below 2^20
+      for (int t = 0; t < gm - 1; ++t) rows *= 2 * v + 1;
+      if (rows > (int64_t(1) << 20)) return false;
+      p.openK = v;
+      p.openMode = (gm == d && (int64_t(v) + 1) * L <= E) ? kModeP16 : kModeI64;
     }
   }
   // Ring steps before the prefix scan: more in more dimensions, where rings
   // stay cheap longer than scanning a long density prefix.
-  p.ring_cap = d <= 2 ? kRingCostCap : 4 * kRingCostCap;
+  p.ring_cap = d <= 2 ? kRingCostCap : kRingCostCapWide;
   {
     const int v = opt ? opt->ring_cap : 0;
     if (v >= 1 && v <= 1 << 20) p.ring_cap = v;
@@ -622,7 +618,7 @@ dpc_status dpc_batch_plan(const dpc_job *jobs, int32_t njobs, const dpc_tuning *
     add_blocks(b->maps[kMapStrips], uint32_t(k), (p.nstrips + kBatchPoints) / kBatchPoints);
     const uint32_t w0 = uint32_t(b->maps[kMapWork].vjob.size());
     // persistent work: about kBatchTasks tasks per virtual block, or in lane form
-    // kBatchLanePoints points (kBlock lanes, a few points each)
+    // kBatchLanePoints points (one per lane)
     add_blocks(b->maps[kMapWork], uint32_t(k),
                p.lanes ? (p.n + kBatchLanePoints - 1) / kBatchLanePoints
                        : std::min<int64_t>(2048, (p.max_tasks + kBatchTasks - 1) / kBatchTasks));

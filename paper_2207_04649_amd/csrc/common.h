@@ -24,11 +24,15 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kBatchPoints = 4096;       // points (or strips) per virtual block of a many-job launch
 constexpr int kBatchCells = 8192;        // table cells per virtual block of a many-job launch
 constexpr int kBatchTasks = 8;           // tasks per virtual block of the persistent kernels
-constexpr int kBatchLanePoints = 1024;   // points per virtual block of lane-form kernels
+constexpr int kBatchLanePoints = 256;    // points per virtual block of lane-form kernels (one per lane)
 enum WorkCounter { kWorkDensity = 0, kWorkSearch, kWorkRing, kWorkPeaks };
 constexpr int kPeakChunk = 256;          // rank-order candidates per prefix-scan work unit
 constexpr int64_t kGridCap = 32768;      // most workgroups of a wave-task launch (16 x the resident 2048)
-constexpr int kRingCostCap = 48;         // default of Plan::ring_cap
+constexpr int kRingCostCap = 48;         // default of Plan::ring_cap up to 2-D
+#ifndef DPC_RING_CAP_WIDE
+#define DPC_RING_CAP_WIDE 192
+#endif
+constexpr int kRingCostCapWide = DPC_RING_CAP_WIDE;  // and beyond 2-D
 
 enum DistMode : int32_t {
   kModeP16 = 0,  // low 16 bits of each coordinate, packed two per word; exact while the
@@ -78,8 +82,8 @@ struct Plan {
   int32_t lanes;     // 1: one query per lane with its own window (sparse data); 0: tasks of 64
                      // queries of one strip sharing a window's candidates (dense data)
   int32_t count_work; // 1: the kernels count their distance tests into DevHeader::work (profiling)
-  int32_t openK;     // lane form: radius of a second window stage over the points the first left
-                     // open (0: none; the ring search then starts from the first stage's block)
+  int32_t openK;     // lane form: radius of an optional second window stage over the points the
+                     // first left open (0: none; the ring search then starts from the first block)
   int32_t openMode;  // DistMode of that stage
   int64_t ncells;    // nc^gm
   int64_t nrows;     // nc^(gm-1)

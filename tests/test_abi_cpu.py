@@ -144,14 +144,14 @@ def test_plan_options_are_checked_and_applied():
     with pytest.raises(dpc.DpcError):
         dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(65, 1)]))
     assert dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(0, 1)]))["stages"] == 1  # ball stage
-    # the open-point stage of the lane form: twice the first radius by default
-    assert dpc.dpc_plan_tuned(5000, 4, 1500.0, dpc.Tuning.make(lanes=2))["open_radius"] == 2
-    assert dpc.dpc_plan_tuned(5000, 4, 1500.0, dpc.Tuning.make(lanes=2, open_radius=-1))["open_radius"] == 0
+    # the optional open-point stage of the lane form (off by default)
+    assert dpc.dpc_plan_tuned(5000, 4, 1500.0, dpc.Tuning.make(lanes=2))["open_radius"] == 0
+    assert dpc.dpc_plan_tuned(5000, 4, 1500.0, dpc.Tuning.make(lanes=2, open_radius=2))["open_radius"] == 2
     assert dpc.dpc_plan_tuned(5000, 4, 1500.0, dpc.Tuning.make(lanes=2, open_radius=3))["open_radius"] == 3
-    assert dpc.dpc_plan_tuned(5000, 4, 1500.0, dpc.Tuning.make(lanes=1))["open_radius"] == 0
-    for bad in (1, 17, -2):  # not beyond the first block, too wide, unknown
-        with pytest.raises(dpc.DpcError):
-            dpc.dpc_plan_tuned(5000, 4, 1500.0, dpc.Tuning.make(lanes=2, open_radius=bad))
+    for bad in (dict(lanes=2, open_radius=1), dict(lanes=2, open_radius=17), dict(lanes=2, open_radius=-1),
+                dict(lanes=1, open_radius=2), dict(lanes=2, stages=[(0, 1)], open_radius=2)):
+        with pytest.raises(dpc.DpcError):  # not beyond the first block, too wide, unknown, no lane block stage
+            dpc.dpc_plan_tuned(5000, 4, 1500.0, dpc.Tuning.make(**bad))
     with pytest.raises(dpc.DpcError):
         dpc.dpc_plan_tuned(1000, 2, 200.0, dpc.Tuning.make(stages=[(1, 99)]))
 

@@ -131,7 +131,7 @@ def test_emulated_open_stage_hand_over_matches_oracle():
         pts = inputs.uniform_points(n, d, 131071, 700 + k)
         pts[n // 2:] = pts[: n - n // 2] + (pts[: n - n // 2] % 7)
         jobs.append((np.clip(pts, 0, 131071).astype(np.int32), dc, 2, dc * 1.5))
-    outs = run_emu_batch(exe, jobs, "lanes=2")
+    outs = run_emu_batch(exe, jobs, "lanes=2;open=2")
     for k, (job, got) in enumerate(zip(jobs, outs)):
         assert got["status"] == 0 and got["sync"] == 0, k
         pins.assert_same(got, pins.run(scan, *job), keys=("rho", "dep", "delta", "label", "ncenters"), ctx=f"job {k}")
@@ -144,8 +144,8 @@ def test_emulated_open_stage_hand_over_matches_oracle():
     "lanes=2",                         # one query per lane, every dimension
     "lanes=2;stages=2:1;gm=2",         # lane form, radius-2 stage, partial grid
     "lanes=2;subdiv=2;ring=3",
-    "lanes=2;open=-1",                 # lane form without the open-point stage
-    "lanes=2;open=3;ring=2",           # a radius-3 open-point stage, short rings
+    "lanes=2;open=2",                  # lane form with the open-point stage (line path)
+    "lanes=2;open=3;ring=2",           # a radius-3 open-point stage (row path), short rings
     "lanes=1",                         # tasks of 64 queries, every dimension
 ])
 def test_emulated_plan_options_match_oracle(emu_exe, tuning):
