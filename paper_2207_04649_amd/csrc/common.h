@@ -56,7 +56,8 @@ struct DevHeader {
   uint64_t stamp[kStampWords];  // the grid's identity (grid_stamp)
   uint64_t work[4];       // with Plan::count_work: candidate (query, point) distance tests of the
                           // density, window search, ring search and prefix scan kernels
-  uint32_t pad[38];
+  uint32_t rank_end;      // ranks the prefix scan reads: the largest bucket end of a deferred point
+  uint32_t pad[37];
 };
 static_assert(sizeof(DevHeader) == 256, "header is one 256-byte slot");
 
@@ -111,7 +112,8 @@ struct Ws {
   uint4 *tasks;      // [max_tasks] {first query, end query, strip, 0}
   uint32_t *rcnt;    // [n + 1] rho histogram by (n - rho), then bucket starts
   int32_t *rpts;     // [n][d] coordinates in rank order
-  int32_t *rid;      // [n] id at each rank position
+  int32_t *rid;      // [n] cell-order position at each rank position; up to DevHeader::rank_end,
+                     // rewritten with the id there when the rank-order points are gathered
   uint64_t *best;    // [n] packed (D2 << 27 | dep) per cell-order position, kNoKey if none
   uint32_t *unres;   // [n + 1] cell-order positions open after the search stages (+ spare slot)
   uint32_t *peaks;   // [n + 1] cell-order positions left to the rank-prefix scan (+ spare slot)
@@ -210,6 +212,7 @@ hipError_t gather_rank_keys(const Plan &p, const Ws &w, const int32_t *rho, hipS
 hipError_t launch_density(const Plan &p, const Ws &w, hipStream_t s);
 hipError_t write_rho(const Plan &p, const Ws &w, int32_t *rho, hipStream_t s);
 hipError_t rank_sort(const Plan &p, const Ws &w, hipStream_t s);
+hipError_t launch_rank_gather(const Plan &p, const Ws &w, hipStream_t s);  // after the ring search
 // Dependent points; the outputs (and rho, if not null) are written in id order.
 hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, int32_t *rho, hipStream_t s);
 hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const double *delta,
@@ -221,6 +224,7 @@ hipError_t batch_start(const BatchMaps &B, hipStream_t s);
 hipError_t batch_build_grid(const BatchMaps &B, hipStream_t s);
 hipError_t batch_density(const BatchMaps &B, hipStream_t s);
 hipError_t batch_rank(const BatchMaps &B, hipStream_t s);
+hipError_t batch_rank_gather(const BatchMaps &B, hipStream_t s);  // after the ring search
 hipError_t batch_dependent(const BatchMaps &B, hipStream_t s);
 hipError_t batch_label(const BatchMaps &B, hipStream_t s);
 hipError_t clear_status(DevHeader *hdr, hipStream_t s);

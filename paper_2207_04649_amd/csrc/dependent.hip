@@ -958,6 +958,7 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
     if (uniform(defer ? 1u : 0u) != 0u) {
       const uint32_t slot = uniform(wave_append(&w.hdr->n_peaks, lane == 0));
       w.peaks[slot] = q;
+      if (lane == 0) atomicMax(&w.hdr->rank_end, prefix);  // the ranks its prefix scan reads
     }
   }
   if (p.count_work) add_work(w.hdr, kWorkRing, lane == 0 ? work : 0);
@@ -1224,6 +1225,8 @@ hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta,
   }
   {
     ProfScope ps(s, kProfPeaks);
+    hipError_t e = launch_rank_gather(p, w, s);
+    if (e != hipSuccess) return e;
     DPC_LAUNCH((k_peaks<D>), rb, kBlock, s, p, w);
   }
   ProfScope ps(s, kProfFinish);
@@ -1257,11 +1260,10 @@ void batch_dep_group(const BatchMaps &B, const VMap &m, int what, int st, hipStr
   } else if (what == 2) {
     ProfScope ps(s, kProfOpen);
     DPC_LAUNCH((kb_search_open<DD>), vgrid(m), kBlock, s, B.jobs, m);
+  } else if (what == 1) {
+    ProfScope ps(s, kProfRingK);
+    DPC_LAUNCH((kb_ringk<DD>), vgrid(m), kBlock, s, B.jobs, m);
   } else {
-    {
-      ProfScope ps(s, kProfRingK);
-      DPC_LAUNCH((kb_ringk<DD>), vgrid(m), kBlock, s, B.jobs, m);
-    }
     ProfScope ps(s, kProfPeaks);
     DPC_LAUNCH((kb_peaks<DD>), vgrid(m), kBlock, s, B.jobs, m);
   }
@@ -1301,6 +1303,11 @@ hipError_t batch_dependent(const BatchMaps &B, hipStream_t s) {
   }
   if (B.any_open && (e = batch_groups(B, 2, 0, s)) != hipSuccess) return e;
   if ((e = batch_groups(B, 1, 0, s)) != hipSuccess) return e;
+  {
+    ProfScope ps(s, kProfPeaks);
+    if ((e = batch_rank_gather(B, s)) != hipSuccess) return e;
+  }
+  if ((e = batch_groups(B, 3, 0, s)) != hipSuccess) return e;
   ProfScope ps(s, kProfFinish);
   if (vgrid(B.pts)) DPC_LAUNCH((kb_finish), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   return hipGetLastError();

@@ -325,23 +325,26 @@ __device__ __forceinline__ void rank_hist(Blk k, const Plan &p, const uint64_t *
 }
 
 // Rank order in two passes, like the grid: each cell-order position q stores
-// itself at its rank position (one scattered 4-byte store; the prefix-scan list
-// is free until the ring search), then every rank position copies its point
-// and id from there (contiguous stores, gathered reads).
+// itself at its rank position in rid (one scattered 4-byte store) ...
 __device__ __forceinline__ void rank_scatter(Blk k, const Plan &p, const Ws &w) {
   if (grid_skipped(w.hdr)) return;
   for (int64_t q = thread_index(k); q < p.n; q += grid_threads(k)) {
     int64_t rho = int64_t(w.sK[q] >> 32);
     rho = rho < 1 ? 1 : (rho > p.n ? p.n : rho);
-    w.peaks[int64_t(w.rcnt[p.n - rho]) + w.slot[q]] = uint32_t(q);
+    w.rid[int64_t(w.rcnt[p.n - rho]) + w.slot[q]] = int32_t(q);
   }
 }
 
+// ... and, once the ring search has deferred its points, every rank position
+// the prefix scan will read (below DevHeader::rank_end, usually a short run of
+// the densest ranks) copies its point and id from there (contiguous stores,
+// gathered reads; in place in rid).
 __device__ __forceinline__ void rank_gather(Blk k, const Plan &p, const Ws &w) {
   if (grid_skipped(w.hdr)) return;
+  const int64_t end = int64_t(uniform(as_const(&w.hdr->rank_end)[0]));
   const bool v4 = p.d == 4;  // 16-byte rows (the arrays are 256-byte aligned)
-  for (int64_t r = thread_index(k); r < p.n; r += grid_threads(k)) {
-    const uint32_t q = w.peaks[r];
+  for (int64_t r = thread_index(k); r < end; r += grid_threads(k)) {
+    const uint32_t q = uint32_t(w.rid[r]);
     if (v4) {
       reinterpret_cast<int4 *>(w.rpts)[r] = reinterpret_cast<const int4 *>(w.spts)[q];
     } else {
@@ -362,6 +365,7 @@ __device__ __forceinline__ void reset_hdr(DevHeader *hdr, int grid) {
     hdr->n_unres = 0;
     hdr->n_peaks = 0;
     hdr->n_ring = 0;
+    hdr->rank_end = 0;
   }
 }
 
@@ -619,7 +623,11 @@ hipError_t rank_sort(const Plan &p, const Ws &w, hipStream_t s) {
   DPC_LAUNCH((k_rank_hist), blocks_for(p.n, int(kRankChunk)), kBlock, s, p, w);
   if ((e = launch_scan(w.rcnt, p.n + 1, w.bsum, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_rank_scatter), blocks_for(p.n, kBlock), kBlock, s, p, w);
-  DPC_LAUNCH((k_rank_gather), blocks_for(p.n, kBlock), kBlock, s, p, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_gather(const Plan &p, const Ws &w, hipStream_t s) {
+  DPC_LAUNCH((k_rank_gather), blocks_for(p.n, kBlock * 8), kBlock, s, p, w);
   return hipGetLastError();
 }
 
@@ -651,6 +659,10 @@ hipError_t batch_rank(const BatchMaps &B, hipStream_t s) {
   }
   batch_scan<kArrRank>(B, B.pts, s);
   if (vgrid(B.pts)) DPC_LAUNCH((kb_rank_scatter), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
+  return hipGetLastError();
+}
+
+hipError_t batch_rank_gather(const BatchMaps &B, hipStream_t s) {
   if (vgrid(B.pts)) DPC_LAUNCH((kb_rank_gather), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   return hipGetLastError();
 }

@@ -312,6 +312,11 @@ inline unsigned long long atomicMin(unsigned long long *p, unsigned long long v)
   if (v < old) *p = v;
   return old;
 }
+inline unsigned atomicMax(unsigned *p, unsigned v) {
+  unsigned old = *p;
+  if (v > old) *p = v;
+  return old;
+}
 
 // Runtime calls used by the host side of the library: memory is host memory.
 inline hipError_t hipGetLastError() { return hipSuccess; }
