@@ -312,6 +312,9 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   p.o_flag = take(size_t(n));
   p.o_srec = 0;
   if (p.lanes && d <= 4 && p.stageMode[0] == kModeP16) p.o_srec = take(size_t(n) * 16);
+  // one bit per 8 cells, written whole by the table scan (every word of every
+  // 4096-cell scan tile)
+  p.o_occ = take(size_t((p.ncells + 1 + kScanTile - 1) / kScanTile) * (kScanTile / 256) * 4);
   p.total = o;
   *out = p;
   return true;

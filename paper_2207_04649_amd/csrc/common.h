@@ -92,7 +92,7 @@ struct Plan {
   int64_t max_tasks;
   // workspace byte offsets
   size_t o_hdr, o_cnt, o_bsum, o_key, o_slot, o_spts, o_spk, o_sid, o_sK, o_tcnt, o_tasks, o_rcnt,
-      o_rpts, o_rid, o_best, o_unres, o_peaks, o_flag, o_srec, total;
+      o_rpts, o_rid, o_best, o_unres, o_peaks, o_flag, o_srec, o_occ, total;
 };
 
 // Pointers into one workspace, resolved from a Plan.
@@ -118,6 +118,8 @@ struct Ws {
   uint32_t *unres;   // [n + 1] cell-order positions open after the search stages (+ spare slot)
   uint32_t *peaks;   // [n + 1] cell-order positions left to the rank-prefix scan (+ spare slot)
   uint8_t *flag;     // [n] 1 while the cell-order position's dependent point is open
+  uint32_t *occ;     // [ceil(ncells / 256)] cell occupancy: bit g (word g / 32) is set when one of
+                     // the 8 cells 8g .. 8g + 7 (flat table index) holds a point
   uint4 *srec;       // [n] lane form with packed coordinates of d <= 4: per cell-order position
                      // {packed words (one or two), rank key low, rank key high}, what a lane
                      // search reads of a candidate in one 16-byte load (null otherwise)
@@ -145,6 +147,7 @@ inline Ws resolve(const Plan &p, void *base) {
   w.peaks = reinterpret_cast<uint32_t *>(b + p.o_peaks);
   w.flag = reinterpret_cast<uint8_t *>(b + p.o_flag);
   w.srec = p.o_srec ? reinterpret_cast<uint4 *>(b + p.o_srec) : nullptr;
+  w.occ = reinterpret_cast<uint32_t *>(b + p.o_occ);
   return w;
 }
 
@@ -200,7 +203,7 @@ struct GridStamp {
 
 // Host-side launch helpers (implemented in the .hip files).
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
-hipError_t launch_scan(uint32_t *data, int64_t count, uint32_t *bsum, hipStream_t s);
+hipError_t launch_scan(uint32_t *data, int64_t count, uint32_t *bsum, hipStream_t s, uint32_t *occ = nullptr);
 // Grid: cell keys, counting sort into cells, cell-order copies, strip tasks; stamps the header.
 hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, const GridStamp &stamp, hipStream_t s);
 // Checks the header's stamp against `stamp` (a reused grid): on a mismatch every grid kernel

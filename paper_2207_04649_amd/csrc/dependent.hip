@@ -845,19 +845,23 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
                 if (xa > 0.0f) lo_s = max(lo_s, int32_t(xa * inv_l * (1.0f - 0x1p-20f)));
                 if (xz < float(DPC_COORD_LIMIT)) hi_s = min(hi_s, int32_t(xz * inv_l * (1.0f + 0x1p-20f)));
               }
+              // (in lane form, meant for sparse data, a piece of empty cells, the
+              // common case in a sparse annulus, is skipped by its occupancy bits
+              // without touching the table)
               const int32_t base = rowk * nc;
+              auto occupied = [&](int32_t a, int32_t b) { return !p.lanes || cells_occupied(w.occ, base + a, base + b); };
               if (outer) {  // the whole row lies outside the block searched so far
-                if (lo_s <= hi_s) {
+                if (lo_s <= hi_s && occupied(lo_s, hi_s)) {
                   const uint32_t b = w.cnt[base + lo_s];
                   sg[2 * i] = make_uint2(b, w.cnt[base + hi_s + 1] - b);
                 }
               } else {  // two pieces: left and right of the searched block
                 const int32_t l_hi = min(hi_s, cl - k0 - 1), r_lo = max(lo_s, cl + k0 + 1);
-                if (lo_s <= l_hi) {
+                if (lo_s <= l_hi && occupied(lo_s, l_hi)) {
                   const uint32_t b = w.cnt[base + lo_s];
                   sg[2 * i] = make_uint2(b, w.cnt[base + l_hi + 1] - b);
                 }
-                if (r_lo <= hi_s) {
+                if (r_lo <= hi_s && occupied(r_lo, hi_s)) {
                   const uint32_t b = w.cnt[base + r_lo];
                   sg[2 * i + 1] = make_uint2(b, w.cnt[base + hi_s + 1] - b);
                 }
@@ -1088,10 +1092,8 @@ template <int D, int MODE>
 __global__ __launch_bounds__(kBlock) void k_search(Plan p, Ws w, int K, int group, int first) {
   search_body<D, MODE>(grid_blk(), p, w, K, group, first);
 }
-// Stage 0 covers every point with a grid sized to them, renumbered per XCD; the
-// list stages run on a grid sized for the worst case, most of whose blocks find
-// nothing to do, so their blocks keep the dispatcher's order (renumbering would
-// put all the work on one XCD).
+// The lane-form stage covers every point with a grid sized to them, its blocks
+// renumbered per XCD (neighbouring points share an L2).
 template <int D, int MODE>
 __global__ __launch_bounds__(kBlock) DPC_WAVES(DPC_SEARCH_WAVES) void k_search_lanes(Plan p, Ws w, int K) {
   search_lanes<D, MODE>(xcd_blk(), p, w, K);

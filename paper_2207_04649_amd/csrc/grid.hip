@@ -40,9 +40,23 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *t
 
 static_assert(kScanItems % 4 == 0, "the scan moves whole tiles in 16-byte vectors");
 
+// Bit i of x at bit 2i (16 bits spread over 32).
+__device__ __forceinline__ uint32_t spread_bits16(uint32_t x) {
+  x &= 0xFFFFu;
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
 // Exclusive scan of u32 in three passes over tiles of kScanTile items:
-// tile-local scans with each tile's total written to bsum ...
-__device__ __forceinline__ void scan_tiles(Blk k, uint32_t *data, int64_t count, uint32_t *bsum) {
+// tile-local scans with each tile's total written to bsum ...  With `occ`, the
+// pass also writes the occupancy bits of the counts it scans: bit g set when one
+// of the 8 counts 8g .. 8g + 7 is nonzero (a lane's 16 counts are two groups, a
+// wave's 1024 counts four whole words, each written once).
+__device__ __forceinline__ void scan_tiles(Blk k, uint32_t *data, int64_t count, uint32_t *bsum,
+                                           uint32_t *occ = nullptr) {
   const int64_t tiles = (count + kScanTile - 1) / kScanTile;
   for (int64_t t = k.b; t < tiles; t += k.nb) {
     const int64_t base = t * kScanTile + int64_t(threadIdx.x) * kScanItems;
@@ -71,6 +85,22 @@ __device__ __forceinline__ void scan_tiles(Blk k, uint32_t *data, int64_t count,
     }
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) sum += v[j];
+    if (occ) {
+      static_assert(kScanItems == 16, "two 8-cell groups per lane");
+      uint32_t lo = 0, hi = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        lo |= v[j];
+        hi |= v[8 + j];
+      }
+      const uint64_t m0 = __ballot(lo != 0), m1 = __ballot(hi != 0);
+      const int lane = lane_id();
+      if (lane < 4) {  // word `lane` of the wave: groups 32 lane .. 32 lane + 31
+        const uint32_t e0 = uint32_t(m0 >> (16 * lane)), e1 = uint32_t(m1 >> (16 * lane));
+        const int64_t word = (t * kScanTile + int64_t(threadIdx.x / kWave) * (kWave * kScanItems)) / 256 + lane;
+        occ[word] = spread_bits16(e0) | (spread_bits16(e1) << 1);
+      }
+    }
     uint32_t total;
     uint32_t run = block_exclusive_scan(sum, &total);
     if (vec) {
@@ -374,8 +404,8 @@ __device__ __forceinline__ void reset_hdr(DevHeader *hdr, int grid) {
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, int64_t count) {
   fill_u32(grid_blk(), p, v, count);
 }
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *data, int64_t count, uint32_t *bsum) {
-  scan_tiles(grid_blk(), data, count, bsum);
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *data, int64_t count, uint32_t *bsum, uint32_t *occ) {
+  scan_tiles(grid_blk(), data, count, bsum, occ);
 }
 __global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t *bsum, int64_t count) { scan_sums(bsum, count); }
 __global__ __launch_bounds__(kBlock) void k_scan_add(uint32_t *data, int64_t count, const uint32_t *bsum) {
@@ -479,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void kb_scan_tiles(const JobDev *jobs, VMap
   uint32_t *data;
   int64_t count;
   scan_target<A>(p, w, &data, &count);
-  scan_tiles(k, data, count, w.bsum);
+  scan_tiles(k, data, count, w.bsum, A == kArrCells ? w.occ : nullptr);
 }
 }
 
@@ -573,10 +603,10 @@ hipError_t launch_fill_u32(uint32_t *ptr, uint32_t value, int64_t count, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_scan(uint32_t *data, int64_t count, uint32_t *bsum, hipStream_t s) {
+hipError_t launch_scan(uint32_t *data, int64_t count, uint32_t *bsum, hipStream_t s, uint32_t *occ) {
   if (count <= 0) return hipSuccess;
   const unsigned tiles = blocks_for(count, kScanTile);
-  DPC_LAUNCH((k_scan_tiles), tiles, kBlock, s, data, count, bsum);
+  DPC_LAUNCH((k_scan_tiles), tiles, kBlock, s, data, count, bsum, occ);
   DPC_LAUNCH((k_scan_sums), 1, kBlock, s, bsum, count);
   DPC_LAUNCH((k_scan_add), tiles, kBlock, s, data, count, bsum);
   return hipGetLastError();
@@ -602,7 +632,7 @@ hipError_t build_grid(const Plan &p, const Ws &w, const int32_t *pts, const Grid
   DPC_LAUNCH((k_stamp_grid), 1, kWave, s, w.hdr, stamp);
   if ((e = launch_fill_u32(w.cnt, 0u, p.ncells + 1, s)) != hipSuccess) return e;
   DPC_LAUNCH((k_cell_keys), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
-  if ((e = launch_scan(w.cnt, p.ncells + 1, w.bsum, s)) != hipSuccess) return e;
+  if ((e = launch_scan(w.cnt, p.ncells + 1, w.bsum, s, w.occ)) != hipSuccess) return e;
   DPC_LAUNCH((k_scatter), blocks_for(p.n, kBlock), kBlock, s, p, w);
   DPC_LAUNCH((k_gather_pts), blocks_for(p.n, kBlock), kBlock, s, pts, p, w);
   if (p.lanes) return hipGetLastError();  // one query per lane: no strip tasks

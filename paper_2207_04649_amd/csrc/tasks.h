@@ -341,6 +341,18 @@ __device__ __forceinline__ uint64_t exact_d2_u(const int32_t *a, const int32_t *
   return s;
 }
 
+// False when none of the table cells c0 .. c1 (flat indices, c0 <= c1) holds a
+// point, by the occupancy bits (one per 8 cells): a row piece of empty cells then
+// needs no table lookup.  Pieces wider than 32 groups are taken as occupied.
+__device__ __forceinline__ bool cells_occupied(const uint32_t *__restrict__ occ, int32_t c0, int32_t c1) {
+  const uint32_t ga = uint32_t(c0) >> 3, gb = uint32_t(c1) >> 3;
+  if (gb - ga >= 32u) return true;
+  const uint32_t w0 = occ[ga >> 5], w1 = occ[gb >> 5];
+  const uint64_t bits = ((uint64_t(w1) << 32) | w0) >> (ga & 31u);  // w1 == w0 when one word holds both
+  const uint64_t mask = (uint64_t(2) << (gb - ga)) - 1u;
+  return (((ga >> 5) == (gb >> 5) ? uint64_t(w0 >> (ga & 31u)) : bits) & mask) != 0u;
+}
+
 constexpr int ipow3(int e) { return e <= 0 ? 1 : 3 * ipow3(e - 1); }
 
 // Rows of a radius-1 window whose candidate ranges one lane queues in LDS before
@@ -350,6 +362,7 @@ constexpr int walk_chunk() {
   return ipow3(D - 1) < 9 ? ipow3(D - 1) : 9;
 }
 constexpr int kWalkQueue = 9;  // LDS queue entries per lane (walk_chunk<D>() <= this)
+
 
 
 // The radius-1 window of a lane's cell when every coordinate is indexed (gm ==
