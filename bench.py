@@ -94,7 +94,21 @@ def rooflines(job, per_ms: dict, sum_rho: int, work: dict, plan: dict) -> dict:
 # sources they were taken with: when those change, traffic is reported as null.
 KERNEL_SOURCES = ("paper_2207_04649_amd/csrc/density.hip", "paper_2207_04649_amd/csrc/dependent.hip",
                   "paper_2207_04649_amd/csrc/grid.hip", "paper_2207_04649_amd/csrc/tasks.h",
-                  "paper_2207_04649_amd/csrc/common.h")
+                  "paper_2207_04649_amd/csrc/common.h", "paper_2207_04649_amd/csrc/api.hip",
+                  "paper_2207_04649_amd/csrc/label.hip")
+# The kernels of each timed group (one step of dpc_run), for summing their counters.
+GROUP_KERNELS = {
+    "grid_build": ("k_stamp_grid", "k_fill_u32", "k_cell_keys", "k_scan_tiles", "k_scan_sums", "k_scan_add",
+                   "k_scatter", "k_gather_pts", "k_strip_count", "k_strip_tasks", "k_zero_count"),
+    "density": ("k_density", "k_density_lanes"),
+    "rank_sort": ("k_rank_hist", "k_rank_scatter"),
+    "search": ("k_search", "k_search_lanes", "k_collect"),
+    "open_search": ("k_search_open",),
+    "ringk": ("k_ringk",),
+    "peaks": ("k_rank_gather", "k_peaks"),
+    "finish": ("k_finish",),
+    "label": ("k_label_init", "k_jump", "k_root"),
+}
 HBM_BYTES: dict = {}  # {workload: {"source": hash, group: bytes per launch}}
 
 
@@ -463,7 +477,7 @@ def bench_single(args, job, steps: int, warmup: int, with_roofline: bool) -> dic
     work = _report(L)["work"]
     dpc.dpc_sync_status(ws)
 
-    per = {k: v[1] / max(1, v[0]) for k, v in prof.items() if k != "work" and v[0]}
+    per = {k: v[1] / steps for k, v in prof.items() if k != "work" and v[0]}  # each group's ms per step
     sum_rho = int(out["rho"].sum().item())
     plan = dpc.dpc_plan(job.n, job.d, job.d_cut)
     roofs = rooflines(job, per, sum_rho, work, plan)

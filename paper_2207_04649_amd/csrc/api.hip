@@ -200,6 +200,7 @@ bool make_plan(int64_t n, int32_t d, double d_cut, const dpc_tuning *opt, Plan *
   // Strip width: a window of radius K around a strip spans at most (wc + 2K)
   // cells in the last dimension; the packed 16-bit path needs that below E.
   const int64_t E = p16_extent(d);
+  p.ext16 = int32_t(E);
   auto p16_ok = [&](int64_t K, int64_t wc) { return wc >= 1 && (wc + 2 * K) * L <= E && (2 * K + 1) * L <= E; };
   const int64_t wc16 = E / L - 2 * int64_t(p.K0);
   // The packed path needs every coordinate difference bounded by the window,

@@ -86,6 +86,8 @@ struct Plan {
   int32_t openK;     // lane form: radius of an optional second window stage over the points the
                      // first left open (0: none; the ring search then starts from the first block)
   int32_t openMode;  // DistMode of that stage
+  int32_t ext16;     // E: the packed 16-bit distance path is exact while every coordinate
+                     // difference is below E (E - 1 <= 32767, d (E - 1)^2 < 2^31)
   int64_t ncells;    // nc^gm
   int64_t nrows;     // nc^(gm-1)
   int64_t nstrips;   // nrows * nsx

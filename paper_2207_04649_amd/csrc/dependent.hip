@@ -716,6 +716,10 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
   DPC_CONST(uint32_t) *rstart = as_const(w.rcnt);
   const int32_t L = p.L, nc = p.nc;
   const int nr = p.gm - 1;  // row dimensions
+  constexpr int W = (D + 1) / 2;
+  // packed candidate records (lane form with the packed path, d <= 4, every
+  // coordinate indexed)
+  const bool use_rec = W <= 2 && w.srec != nullptr && p.gm == D;
 
   uint64_t work = 0;  // candidate tests (wave-uniform; profiling)
   const uint32_t nw = grid_waves(blk);
@@ -729,6 +733,9 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
       c[k] = x[k] / L;
     }
     const int32_t xs = uniform(spc[int64_t(q) * D + nr]);  // coordinate along the strip dimension
+    uint32_t qk[W];  // its packed words, for the packed candidate records
+#pragma unroll
+    for (int k = 0; k < W; ++k) qk[k] = use_rec ? uniform(as_const(w.spk)[int64_t(q) * W + k]) : 0u;
     const int32_t cl = xs / L;
     const uint64_t Ki = uniform(sKc[q]);
     const int64_t rho = int64_t(Ki >> 32);
@@ -773,6 +780,9 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
       }
       int32_t sa, sb;
       box(xs, cl, &sa, &sb);
+      // The packed 16-bit records serve while every candidate of the block lies
+      // within (k1 + 1) L - 1 of the point in each coordinate, all of them indexed.
+      const bool packed = use_rec && (int64_t(k1) + 1) * L <= int64_t(p.ext16);
       // A pass costs at least kRingRows per round: one that cannot end within the
       // budget defers the point at once.
       constexpr uint32_t kStride = kWave * kRingRows;  // rows per round
@@ -918,17 +928,32 @@ __device__ __forceinline__ void ringk_body(Blk blk, const Plan &p, const Ws &w, 
             }
             pos[h] = have[h] ? at : 0u;
           }
-          uint64_t kj[2];
-          int32_t y[2][D];
+          uint64_t kj[2], d2[2];
+          if (packed) {  // one 16-byte record per candidate
+            uint4 rec[2];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            kj[h] = w.sK[pos[h]];
+            for (int h = 0; h < 2; ++h) rec[h] = w.srec[pos[h]];
 #pragma unroll
-            for (int t = 0; t < D; ++t) y[h][t] = w.spts[int64_t(pos[h]) * D + t];
+            for (int h = 0; h < 2; ++h) {
+              kj[h] = (uint64_t(rec[h].w) << 32) | rec[h].z;
+              int32_t a = dot2_self_v(pk_sub16(qk[0], rec[h].x), 0);
+              if (W == 2) a = dot2_self_v(pk_sub16(qk[W - 1], rec[h].y), a);
+              d2[h] = uint32_t(a);
+            }
+          } else {
+            int32_t y[2][D];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              kj[h] = w.sK[pos[h]];
+#pragma unroll
+              for (int t = 0; t < D; ++t) y[h][t] = w.spts[int64_t(pos[h]) * D + t];
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) d2[h] = exact_d2_u<D>(x, y[h]);
           }
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const uint64_t key = (exact_d2_u<D>(x, y[h]) << kIdBits) | uint32_t(~uint32_t(kj[h]));
+            const uint64_t key = (d2[h] << kIdBits) | uint32_t(~uint32_t(kj[h]));
             lbest = (have[h] && kj[h] > Ki && key < lbest) ? key : lbest;
           }
         }
@@ -1209,7 +1234,7 @@ hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta,
   }
   const unsigned rb = persistent_blocks(p.n);
   {
-    ProfScope ps(s, kProfRingK);
+    ProfScope ps(s, kProfSearch);  // the open points' list closes the window search
     DPC_LAUNCH((k_collect), blocks_for(p.n, kBlock * kCollectPer), kBlock, s, p, w);
   }
   if (p.openK) {  // kOpenLanes lanes per open point: up to 16 points each if all were open
@@ -1300,7 +1325,7 @@ hipError_t batch_dependent(const BatchMaps &B, hipStream_t s) {
       if ((e = batch_groups(B, 0, st, s)) != hipSuccess) return e;
   }
   {
-    ProfScope ps(s, kProfRingK);
+    ProfScope ps(s, kProfSearch);
     if (vgrid(B.pts)) DPC_LAUNCH((kb_collect), vgrid(B.pts), kBlock, s, B.jobs, B.pts);
   }
   if (B.any_open && (e = batch_groups(B, 2, 0, s)) != hipSuccess) return e;
