@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 output, per kernel.
 
     python -m paper_2207_04649_amd.prof_summary trace RESULTS_DB [command...]
-        kernel-trace summary (calls, average / min / max microseconds, total ms)
+        kernel-trace summary (calls, average / median / min / max microseconds,
+        total ms)
         from the rocpd SQLite file of ``rocprofv3 --kernel-trace``;
 
     python -m paper_2207_04649_amd.prof_summary hbm FETCH_CSV WRITE_CSV MIB [command...]
@@ -28,19 +29,29 @@ def short_name(name: str) -> str:
 
 
 def summary(db: str) -> list[tuple]:
+    """[(kernel, calls, avg, median, min, max microseconds, total milliseconds)], by total."""
     c = sqlite3.connect(db)
-    rows = c.execute("select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
-                     "from kernels group by name order by sum(duration) desc").fetchall()
-    return [(short_name(n), cnt, avg / 1e3, mn / 1e3, mx / 1e3, tot / 1e6) for n, cnt, avg, mn, mx, tot in rows]
+    durs = collections.defaultdict(list)
+    for name, dur in c.execute("select name, duration from kernels"):
+        durs[name].append(dur)
+    rows = []
+    for name, d in durs.items():
+        d = sorted(d)
+        med = d[len(d) // 2] if len(d) % 2 else (d[len(d) // 2 - 1] + d[len(d) // 2]) / 2
+        rows.append((short_name(name), len(d), sum(d) / len(d) / 1e3, med / 1e3, d[0] / 1e3, d[-1] / 1e3,
+                     sum(d) / 1e6))
+    rows.sort(key=lambda r: -r[6])
+    return rows
 
 
 def render_trace(db: str, command: str = "") -> str:
     out = []
     if command:
         out.append(f"command: {command}")
-    out.append(f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_ms':>10s}")
-    for n, cnt, avg, mn, mx, tot in summary(db):
-        out.append(f"{n[:40]:40s} {cnt:6d} {avg:10.2f} {mn:10.2f} {mx:10.2f} {tot:10.3f}")
+    out.append(f"{'kernel':40s} {'calls':>6s} {'avg_us':>10s} {'median_us':>10s} {'min_us':>10s} {'max_us':>10s} "
+               f"{'total_ms':>10s}")
+    for n, cnt, avg, med, mn, mx, tot in summary(db):
+        out.append(f"{n[:40]:40s} {cnt:6d} {avg:10.2f} {med:10.2f} {mn:10.2f} {mx:10.2f} {tot:10.3f}")
     return "\n".join(out)
 
 
