@@ -109,6 +109,34 @@ dpc_status dpc_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32
                    int64_t *ncenters, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Approx-DPC (Section 4): the same exact local densities, approximate dependent
+ * points where Section 4.3's rules find a denser point close by, exact ones
+ * (Defs. 2-3) elsewhere, then labels (Defs. 4-6) as dpc_label computes them.
+ * Cells of a second grid (Section 4.1) have side La = 1 + floor(sqrt((R - 1) / d)),
+ * R = ceil(d_cut^2): the largest integer side that keeps two points of one cell
+ * strictly within d_cut; a point's cell is (x_1 / La, ..., x_d / La), and its
+ * cell's densest point p*(c) ranks first by (rho descending, id ascending).
+ *   - a point other than p*(c) gets dep = p*(c), delta = d_cut;
+ *   - p*(c) gets dep = p*(c') and delta = d_cut for the cell c' with the smallest
+ *     coordinates (first dimension most significant) among the cells that hold a
+ *     point strictly within d_cut of it and whose points all have a higher rho;
+ *   - any other point gets its exact dependent point and distance.
+ * With delta_min > d_cut (required, as for dpc_run) the centers and the noise
+ * equal dpc_run's (Section 4.4, the cluster center guarantee).
+ *   rho, dep, delta, label, ncenters  as for dpc_run (device)
+ *   approx  optional [n] uint8 output (NULL: not written): 1 where dep and delta
+ *           come from the approximation rules, else 0
+ *   ws      device workspace of at least dpc_approx_workspace_bytes(n, d, d_cut)
+ *           bytes (more than dpc_run's: a hash table of the occupied cells)
+ * Errors: those of dpc_run; DPC_EWORKSPACE when ws_bytes is too small.  Device-
+ * detected problems are read with dpc_sync_status, as for dpc_run.
+ */
+size_t dpc_approx_workspace_bytes(int64_t n, int32_t d, double d_cut);
+dpc_status dpc_approx_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                          double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
+                          int64_t *ncenters, uint8_t *approx, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * dpc_run for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation and outputs as dpc_run, with the scratch space in a static device

@@ -31,7 +31,7 @@ int64_t g_work[5] = {0, 0, 0, 0, 0};
 // candidate distance tests of the last call's density, window search, ring search and prefix scan
 int64_t g_tests[4] = {0, 0, 0, 0};
 const char *kProfNames[kProfCount] = {"grid_build", "density", "rank_keys", "rank_sort", "search",
-                                      "open_search", "ringk", "peaks", "finish", "label"};
+                                      "open_search", "ringk", "peaks", "finish", "label", "approx"};
 }  // namespace
 
 bool prof_on() { return g_prof_level > 0; }
@@ -557,6 +557,31 @@ BatchMaps batch_maps(const dpc_batch &b, void *ws) {
 }
 
 }  // namespace
+// Approx-DPC's second grid and its workspace after the exact path's (which it
+// uses as dpc_run does).
+ApproxPlan make_approx_plan(const Plan &p, double d_cut) {
+  ApproxPlan a{};
+  a.La = int32_t(1 + isqrt64((p.R - 1) / p.d));
+  uint64_t slots = 256;
+  while (slots < 2 * uint64_t(p.n)) slots <<= 1;
+  a.mask = uint32_t(slots - 1);
+  a.d_cut = d_cut;
+  size_t o = align_up(p.total);
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  a.o_cnt = take(256);
+  a.o_rep = take(slots * 4);
+  a.o_top = take(slots * 8);
+  a.o_minrho = take(slots * 4);
+  a.o_ent = take(size_t(p.n) * 4);
+  a.o_plist = take(size_t(p.n) * 4);
+  a.total = o;
+  return a;
+}
+
 }  // namespace dpc
 
 using namespace dpc;
@@ -820,6 +845,40 @@ dpc_status dpc_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32
   if ((st = run_dependent(p, w, pts, nullptr, dep, delta, rho, kGridOwn, s)) != DPC_OK) return st;
   ProfScope ps(s, kProfLabel);
   hipError_t e = launch_label(n, rho, dep, delta, rho_min, delta_min, label, ncenters, w.hdr, s);
+  if (e != hipSuccess) return device_fail(e, "label kernels");
+  return DPC_OK;
+}
+
+size_t dpc_approx_workspace_bytes(int64_t n, int32_t d, double d_cut) {
+  Plan p;
+  return make_plan(n, d, d_cut, nullptr, &p) ? make_approx_plan(p, d_cut).total : 0;
+}
+
+dpc_status dpc_approx_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32_t rho_min,
+                          double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
+                          int64_t *ncenters, uint8_t *approx, void *ws, size_t ws_bytes, void *stream) {
+  Plan p;
+  dpc_status st = check_common(pts, n, d, d_cut, ws, ws_bytes, &p);
+  if (st != DPC_OK) return st;
+  const ApproxPlan a = make_approx_plan(p, d_cut);
+  if (ws_bytes < a.total) return fail(DPC_EWORKSPACE, "workspace smaller than dpc_approx_workspace_bytes()");
+  if (!rho || !dep || !delta || !label || !ncenters) return fail(DPC_EINVAL, "null pointer argument");
+  if (rho_min < 0) return fail(DPC_EINVAL, "rho_min must be >= 0");
+  if (std::isnan(delta_min) || !(delta_min > d_cut)) return fail(DPC_EINVAL, "delta_min must exceed d_cut");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Ws w = resolve(p, ws);
+  hipError_t e = clear_status(w.hdr, s);
+  if (e != hipSuccess) return device_fail(e, "status reset");
+  if ((st = run_density(p, w, pts, s)) != DPC_OK) return st;
+  if ((e = reset_counters(w.hdr, false, s)) != hipSuccess) return device_fail(e, "reset");
+  {
+    ProfScope ps(s, kProfRankSort);
+    if ((e = rank_sort(p, w, s)) != hipSuccess) return device_fail(e, "rank sort");
+  }
+  if ((e = launch_approx(p, w, a, ws, dep, delta, rho, approx, s)) != hipSuccess)
+    return device_fail(e, "approximate dependent kernels");
+  ProfScope ps(s, kProfLabel);
+  e = launch_label(n, rho, dep, delta, rho_min, delta_min, label, ncenters, w.hdr, s);
   if (e != hipSuccess) return device_fail(e, "label kernels");
   return DPC_OK;
 }

@@ -1,0 +1,290 @@
+// Approx-DPC (Section 4) on top of the exact path's grid and density kernels.
+//
+// The local densities are exact (Section 4.2); the exact path's kernels
+// compute them.  A second grid of cells of side La (Section 4.1; for integer
+// coordinates La = 1 + floor(sqrt((R - 1) / d)), the largest side that keeps
+// every two points of a cell strictly within d_cut) is built as an open-
+// addressing hash table over the occupied cells: each cell keeps its densest
+// point p*(c) (the largest rank key (rho << 32 | ~id)) and its smallest
+// density.  The rules of Section 4.3 then give most points a dependent point
+// in O(1) or one range search:
+//
+//   * a point that is not its cell's p* takes p*(c);
+//   * p*(c) takes p*(c') of a cell c' that holds a point strictly within d_cut
+//     of it and whose points all have a higher density (the qualifying cell with
+//     the smallest cell coordinates, first dimension most significant);
+//
+// both with the dependent distance d_cut.  The p* points no cell qualifies for
+// go to the exact path's ring search and prefix scan, which start from an empty
+// window (Defs. 2-3).  The paper's own exact step (density-sorted subsets with
+// one kd-tree each, Section 4.3) is replaced by that search: both return the
+// exact dependent point.
+#include "common.h"
+#include "prof.h"
+
+namespace dpc {
+namespace {
+
+constexpr uint32_t kEmpty = 0xffffffffu;
+// D2 field of a packed (D2 << kIdBits | id) key that marks an approximate
+// dependent point: no two in-range points are that far apart
+// (8 (2^17 - 1)^2 < 2^37 - 2), and it differs from kNoKey's.
+constexpr uint64_t kApproxD2 = (uint64_t(1) << (64 - kIdBits)) - 2;
+
+struct AxWs {
+  uint32_t *cnt;    // [4] counters: p* points, approximate by the second rule
+  uint32_t *rep;    // [slots] cell-order position of the point that opened the slot, kEmpty if free
+  uint64_t *top;    // [slots] largest rank key of the cell (its p*), 0 before any point
+  uint32_t *minrho; // [slots] smallest density of the cell
+  uint32_t *ent;    // [n] table slot of each cell-order position
+  uint32_t *plist;  // [n] cell-order positions of the p* points
+};
+
+AxWs ax_resolve(const ApproxPlan &a, void *base) {
+  char *b = static_cast<char *>(base);
+  AxWs x;
+  x.cnt = reinterpret_cast<uint32_t *>(b + a.o_cnt);
+  x.rep = reinterpret_cast<uint32_t *>(b + a.o_rep);
+  x.top = reinterpret_cast<uint64_t *>(b + a.o_top);
+  x.minrho = reinterpret_cast<uint32_t *>(b + a.o_minrho);
+  x.ent = reinterpret_cast<uint32_t *>(b + a.o_ent);
+  x.plist = reinterpret_cast<uint32_t *>(b + a.o_plist);
+  return x;
+}
+
+// Slot hash of a cell's coordinates (multiply-xorshift rounds).
+template <int D>
+__device__ __forceinline__ uint32_t cell_hash(const int32_t *c) {
+  uint64_t h = 0x9E3779B97F4A7C15ull;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    h = (h ^ uint32_t(c[t])) * 0xFF51AFD7ED558CCDull;
+    h ^= h >> 29;
+  }
+  return uint32_t(h ^ (h >> 32));
+}
+
+// Appends the positions of the lanes with `take` to list[*counter ...]: one
+// atomic per wave.  Every lane of the wave calls it (no loop around it).
+__device__ __forceinline__ void wave_push(uint32_t *counter, uint32_t *list, bool take, uint32_t q) {
+  const uint64_t m = __ballot(take);
+  const int lane = lane_id();
+  uint32_t base = 0;
+  if (lane == 0 && m != 0) base = atomicAdd(counter, uint32_t(__popcll(m)));
+  base = __shfl(base, 0, kWave);
+  if (take) list[base + uint32_t(__popcll(m & ((uint64_t(1) << lane) - 1)))] = q;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ax_clear(AxWs x, uint32_t slots) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < 4) x.cnt[i] = 0;
+  if (i < slots) {
+    x.rep[i] = kEmpty;
+    x.top[i] = 0;
+    x.minrho[i] = kEmpty;
+  }
+}
+
+// Each point finds (or opens) its cell's slot, then raises the slot's top key
+// and lowers its smallest density.  Slots only ever go from free to taken, so a
+// stale free slot read is settled by the compare-and-swap, and a taken one is
+// final.  The table has more slots than points, so a free slot always exists.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ax_insert(Plan p, Ws w, ApproxPlan a, AxWs x) {
+  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= p.n || grid_skipped(w.hdr)) return;
+  int32_t c[D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) c[t] = w.spts[q * D + t] / a.La;
+  uint32_t h = cell_hash<D>(c) & a.mask;
+  for (uint32_t probe = 0; probe <= a.mask; ++probe) {
+    uint32_t r = x.rep[h];
+    if (r == kEmpty) {
+      r = atomicCAS(&x.rep[h], kEmpty, uint32_t(q));
+      if (r == kEmpty) break;  // opened by this point
+    }
+    bool same = true;
+#pragma unroll
+    for (int t = 0; t < D; ++t) same = same && w.spts[int64_t(r) * D + t] / a.La == c[t];
+    if (same) break;
+    h = (h + 1) & a.mask;
+  }
+  const uint64_t K = w.sK[q];
+  x.ent[q] = h;
+  atomicMax(reinterpret_cast<unsigned long long *>(&x.top[h]), static_cast<unsigned long long>(K));
+  atomicMin(&x.minrho[h], uint32_t(K >> 32));
+}
+
+// First rule: a point other than its cell's p* takes p*(c).  The p* points are
+// listed for the range search.
+__global__ __launch_bounds__(kBlock) void k_ax_split(Plan p, Ws w, AxWs x) {
+  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (grid_skipped(w.hdr)) return;
+  bool star = false;
+  if (q < p.n) {
+    const uint64_t top = x.top[x.ent[q]];
+    star = top == w.sK[q];
+    if (!star) w.best[q] = (kApproxD2 << kIdBits) | (~uint32_t(top) & kIdMask);
+  }
+  wave_push(&x.cnt[0], x.plist, star, uint32_t(q));
+}
+
+// Second rule, one lane per p* point: a range search of radius d_cut over the
+// exact grid's cells (their first gm coordinates), keeping the qualifying cell
+// with the smallest coordinates.  A point no cell qualifies for gets kNoKey and
+// goes to the ring search's list.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ax_near(Plan p, Ws w, ApproxPlan a, AxWs x) {
+  if (grid_skipped(w.hdr)) return;
+  const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t nstar = x.cnt[0];
+  const bool own = u < nstar;
+  const uint32_t q = own ? x.plist[u] : 0u;
+  bool found = false;
+  if (own) {
+    int32_t xq[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) xq[t] = w.spts[int64_t(q) * D + t];
+    const uint32_t e = x.ent[q];
+    const uint32_t rho = uint32_t(w.sK[q] >> 32);
+    const int32_t L = p.L, nc = p.nc, gm = p.gm, r0 = p.L0;
+    const int last = gm - 1;
+    int32_t lo[D], hi[D], cur[D], bc[D];  // bc: best qualifying cell so far
+    int32_t lo_l = 0, hi_l = 0;           // cell range along the last grid dimension
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      lo[t] = t < gm ? max(xq[t] - r0, 0) / L : 0;
+      hi[t] = t < gm ? min(xq[t] + r0, DPC_COORD_LIMIT - 1) / L : 0;
+      cur[t] = lo[t];
+      bc[t] = 0;
+      if (t == last) {
+        lo_l = lo[t];
+        hi_l = hi[t];
+      }
+    }
+    uint32_t be = 0;
+    for (;;) {
+      // one row: cells lo_l .. hi_l along the last grid dimension are
+      // consecutive in the table, so their points are one run of positions
+      int64_t row = 0;
+#pragma unroll
+      for (int t = 0; t < D; ++t)
+        if (t < last) row = row * nc + cur[t];
+      const int64_t c0 = row * nc + lo_l;
+      const uint32_t j0 = w.cnt[c0], j1 = w.cnt[c0 + (hi_l - lo_l) + 1];
+      for (uint32_t j = j0; j < j1; ++j) {
+        int64_t d2 = 0;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+          const int64_t df = int64_t(w.spts[int64_t(j) * D + t]) - xq[t];
+          d2 += df * df;
+        }
+        if (d2 >= p.R) continue;
+        const uint32_t e2 = x.ent[j];
+        if (e2 == e || x.minrho[e2] <= rho) continue;
+        int32_t cc[D];
+#pragma unroll
+        for (int t = 0; t < D; ++t) cc[t] = w.spts[int64_t(j) * D + t] / a.La;
+        bool less = !found;
+        bool eq = true;
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+          less = less || (eq && cc[t] < bc[t]);
+          eq = eq && cc[t] == bc[t];
+        }
+        if (less) {
+#pragma unroll
+          for (int t = 0; t < D; ++t) bc[t] = cc[t];
+          be = e2;
+          found = true;
+        }
+      }
+      // next row: an odometer over the grid dimensions before the last
+      bool carry = true;
+#pragma unroll
+      for (int t = D - 1; t >= 0; --t) {
+        if (t < last && carry) {
+          if (cur[t] < hi[t]) {
+            ++cur[t];
+            carry = false;
+          } else {
+            cur[t] = lo[t];
+          }
+        }
+      }
+      if (carry) break;
+    }
+    if (found) {
+      w.best[q] = (kApproxD2 << kIdBits) | (~uint32_t(x.top[be]) & kIdMask);
+    } else {
+      w.best[q] = kNoKey;
+    }
+  }
+  wave_push(&w.hdr->n_unres, w.unres, own && !found, q);
+  const uint64_t m = __ballot(own && found);
+  if (lane_id() == 0 && m != 0) atomicAdd(&x.cnt[1], uint32_t(__popcll(m)));
+}
+
+// Outputs in id order: the exact keys as the exact path's finish writes them,
+// approximate ones as (p*, d_cut) with the flag set.
+__global__ __launch_bounds__(kBlock) void k_ax_finish(Plan p, Ws w, double d_cut, int32_t *__restrict__ dep,
+                                                      double *__restrict__ delta, int32_t *__restrict__ rho,
+                                                      uint8_t *__restrict__ approx) {
+  if (grid_skipped(w.hdr)) return;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= p.n) return;
+  const uint32_t q = w.key[i];
+  const uint64_t key = w.best[q];
+  bool ax = false;
+  if (key == kNoKey) {
+    dep[i] = -1;
+    delta[i] = __builtin_huge_val();
+  } else if ((key >> kIdBits) == kApproxD2) {
+    dep[i] = int32_t(key & kIdMask);
+    delta[i] = d_cut;
+    ax = true;
+  } else {
+    dep[i] = int32_t(key & kIdMask);
+    delta[i] = __builtin_sqrt(double(key >> kIdBits));  // correctly rounded (IEEE sqrt)
+  }
+  rho[i] = int32_t(w.sK[q] >> 32);
+  if (approx) approx[i] = ax ? 1 : 0;
+}
+
+template <int D>
+hipError_t launch_cells_d(const Plan &p, const Ws &w, const ApproxPlan &a, const AxWs &x, hipStream_t s) {
+  DPC_LAUNCH((k_ax_insert<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
+  DPC_LAUNCH((k_ax_split), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+  DPC_LAUNCH((k_ax_near<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_approx(const Plan &p, const Ws &w, const ApproxPlan &a, void *base, int32_t *dep,
+                         double *delta, int32_t *rho, uint8_t *approx, hipStream_t s) {
+  const AxWs x = ax_resolve(a, base);
+  hipError_t e;
+  {
+    ProfScope ps(s, kProfApprox);
+    DPC_LAUNCH((k_ax_clear), blocks_for(int64_t(a.mask) + 1, kBlock), kBlock, s, x, a.mask + 1);
+    switch (p.d) {
+      case 1: e = launch_cells_d<1>(p, w, a, x, s); break;
+      case 2: e = launch_cells_d<2>(p, w, a, x, s); break;
+      case 3: e = launch_cells_d<3>(p, w, a, x, s); break;
+      case 4: e = launch_cells_d<4>(p, w, a, x, s); break;
+      case 5: e = launch_cells_d<5>(p, w, a, x, s); break;
+      case 6: e = launch_cells_d<6>(p, w, a, x, s); break;
+      case 7: e = launch_cells_d<7>(p, w, a, x, s); break;
+      case 8: e = launch_cells_d<8>(p, w, a, x, s); break;
+      default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  if ((e = launch_exact_remainder(p, w, s)) != hipSuccess) return e;
+  ProfScope ps(s, kProfFinish);
+  DPC_LAUNCH((k_ax_finish), blocks_for(p.n, kBlock), kBlock, s, p, w, a.d_cut, dep, delta, rho, approx);
+  return hipGetLastError();
+}
+
+}  // namespace dpc

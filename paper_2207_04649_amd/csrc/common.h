@@ -97,6 +97,15 @@ struct Plan {
       o_rpts, o_rid, o_best, o_unres, o_peaks, o_flag, o_srec, o_occ, total;
 };
 
+// Approx-DPC's second grid (cells of side La) and its part of the workspace,
+// which follows the exact path's.
+struct ApproxPlan {
+  int32_t La;        // cell side: 1 + floor(sqrt((R - 1) / d))
+  uint32_t mask;     // hash table slots - 1 (slots: a power of two >= 2n)
+  double d_cut;      // dependent distance given to an approximate dependent point
+  size_t o_cnt, o_rep, o_top, o_minrho, o_ent, o_plist, total;
+};
+
 // Pointers into one workspace, resolved from a Plan.
 struct Ws {
   DevHeader *hdr;
@@ -220,6 +229,15 @@ hipError_t rank_sort(const Plan &p, const Ws &w, hipStream_t s);
 hipError_t launch_rank_gather(const Plan &p, const Ws &w, hipStream_t s);  // after the ring search
 // Dependent points; the outputs (and rho, if not null) are written in id order.
 hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, int32_t *rho, hipStream_t s);
+// The ring search from an empty window, then the prefix scan, over the list
+// w.unres (DevHeader::n_unres entries) a caller filled; each listed position's
+// best key must be kNoKey.
+hipError_t launch_exact_remainder(const Plan &p, const Ws &w, hipStream_t s);
+// Approx-DPC's dependent points after the density kernels and the rank sort:
+// the second grid, the approximation rules, the exact remainder, and the outputs
+// in id order (approx, if not null, gets 1 where the dependent point is approximate).
+hipError_t launch_approx(const Plan &p, const Ws &w, const ApproxPlan &a, void *base, int32_t *dep,
+                         double *delta, int32_t *rho, uint8_t *approx, hipStream_t s);
 hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const double *delta,
                         int32_t rho_min, double delta_min, int32_t *label, int64_t *ncenters,
                         DevHeader *hdr, hipStream_t s);

@@ -1261,6 +1261,20 @@ hipError_t launch_dep_d(const Plan &p, const Ws &w, int32_t *dep, double *delta,
   return hipGetLastError();
 }
 
+template <int D>
+hipError_t remainder_d(const Plan &p, const Ws &w, hipStream_t s) {
+  const unsigned rb = persistent_blocks(p.n);
+  {
+    ProfScope ps(s, kProfRingK);
+    DPC_LAUNCH((k_ringk<D>), rb, kBlock, s, p, w, -1);  // nothing searched yet
+  }
+  ProfScope ps(s, kProfPeaks);
+  hipError_t e = launch_rank_gather(p, w, s);
+  if (e != hipSuccess) return e;
+  DPC_LAUNCH((k_peaks<D>), rb, kBlock, s, p, w);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *delta, int32_t *rho, hipStream_t s) {
@@ -1273,6 +1287,21 @@ hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *de
     case 6: return launch_dep_d<6>(p, w, dep, delta, rho, s);
     case 7: return launch_dep_d<7>(p, w, dep, delta, rho, s);
     case 8: return launch_dep_d<8>(p, w, dep, delta, rho, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_exact_remainder(const Plan &p, const Ws &w, hipStream_t s) {
+  if (p.openK) return hipErrorInvalidValue;  // the ring search would read the open stage's list
+  switch (p.d) {
+    case 1: return remainder_d<1>(p, w, s);
+    case 2: return remainder_d<2>(p, w, s);
+    case 3: return remainder_d<3>(p, w, s);
+    case 4: return remainder_d<4>(p, w, s);
+    case 5: return remainder_d<5>(p, w, s);
+    case 6: return remainder_d<6>(p, w, s);
+    case 7: return remainder_d<7>(p, w, s);
+    case 8: return remainder_d<8>(p, w, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -17,6 +17,7 @@ enum ProfKernel : int {
   kProfPeaks,
   kProfFinish,
   kProfLabel,
+  kProfApprox,     // Approx-DPC's second grid and approximation rules
   kProfCount
 };
 

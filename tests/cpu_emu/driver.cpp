@@ -9,6 +9,9 @@
 // (the status fields are those of the batch calls).  --tuning SPEC (batch only)
 // gives every job the plan options of SPEC, "key=value" items separated by ';':
 // subdiv, strip, ring, gm, lanes, open, and stages=K:group,K:group,...
+//
+// With --approx the single record runs through dpc_approx_run instead, and the
+// output ends with the n approx flags (uint8).
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -126,6 +129,13 @@ int run_batch(const char *inp, const char *outp, const dpc_tuning *tuning) {
 }
 
 int main(int argc, char **argv) {
+  bool approx_mode = false;
+  if (argc == 4 && std::string(argv[1]) == "--approx") {
+    approx_mode = true;
+    argv[1] = argv[2];
+    argv[2] = argv[3];
+    argc = 3;
+  }
   if (argc == 4 && std::string(argv[1]) == "--batch") return run_batch(argv[2], argv[3], nullptr);
   if (argc == 6 && std::string(argv[1]) == "--batch" && std::string(argv[2]) == "--tuning") {
     dpc_tuning t;
@@ -150,13 +160,17 @@ int main(int argc, char **argv) {
   std::vector<int32_t> pts(size_t(n) * d);
   if (std::fread(pts.data(), 4, pts.size(), in) != pts.size()) return 2;
   std::fclose(in);
-  const size_t wsb = dpc_workspace_bytes(n, d, d_cut);
+  const size_t wsb = approx_mode ? dpc_approx_workspace_bytes(n, d, d_cut) : dpc_workspace_bytes(n, d, d_cut);
   void *ws = std::aligned_alloc(256, (wsb + 255) / 256 * 256);
   std::vector<int32_t> rho(n), dep(n), label(n);
   std::vector<double> delta(n);
+  std::vector<uint8_t> approx(n, 2);
   int64_t ncenters = -1;
-  const int32_t st = dpc_run(pts.data(), n, d, d_cut, rho_min, delta_min, rho.data(), dep.data(), delta.data(),
-                             label.data(), &ncenters, ws, wsb, nullptr);
+  const int32_t st = approx_mode
+                         ? dpc_approx_run(pts.data(), n, d, d_cut, rho_min, delta_min, rho.data(), dep.data(),
+                                          delta.data(), label.data(), &ncenters, approx.data(), ws, wsb, nullptr)
+                         : dpc_run(pts.data(), n, d, d_cut, rho_min, delta_min, rho.data(), dep.data(),
+                                   delta.data(), label.data(), &ncenters, ws, wsb, nullptr);
   const int32_t st2 = dpc_sync_status(ws, nullptr);
   std::free(ws);
   FILE *out = std::fopen(argv[2], "wb");
@@ -167,6 +181,7 @@ int main(int argc, char **argv) {
   std::fwrite(dep.data(), 4, n, out);
   std::fwrite(delta.data(), 8, n, out);
   std::fwrite(label.data(), 4, n, out);
+  if (approx_mode) std::fwrite(approx.data(), 1, n, out);
   std::fclose(out);
   return 0;
 }

@@ -317,6 +317,21 @@ inline unsigned atomicMax(unsigned *p, unsigned v) {
   if (v > old) *p = v;
   return old;
 }
+inline unsigned long long atomicMax(unsigned long long *p, unsigned long long v) {
+  unsigned long long old = *p;
+  if (v > old) *p = v;
+  return old;
+}
+inline unsigned atomicMin(unsigned *p, unsigned v) {
+  unsigned old = *p;
+  if (v < old) *p = v;
+  return old;
+}
+inline unsigned atomicCAS(unsigned *p, unsigned cmp, unsigned v) {
+  unsigned old = *p;
+  if (old == cmp) *p = v;
+  return old;
+}
 
 // Runtime calls used by the host side of the library: memory is host memory.
 inline hipError_t hipGetLastError() { return hipSuccess; }

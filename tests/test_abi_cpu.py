@@ -170,3 +170,15 @@ def test_static_entry_rejects_before_any_device_call():
     assert dpc.dpc_workspace_bytes(big, 4, 1500.0) > dpc.STATIC_SCRATCH_BYTES
     assert L.dpc_run_static(*args(big, 4, 1500.0, 1, 9000.0)) == dpc.DPC_EWORKSPACE
     assert b"static array" in L.dpc_last_error()
+
+
+def test_approx_workspace_bytes():
+    lib = dpc.lib()
+    for n, d, dc in [(1, 1, 1.0), (1000, 2, 300.0), (10 ** 6, 4, 1500.0), (5000, 8, 9000.0)]:
+        exact = lib.dpc_workspace_bytes(n, d, dc)
+        approx = lib.dpc_approx_workspace_bytes(n, d, dc)
+        # a hash table of at least 2n slots of 16 bytes, plus two lists of n entries
+        assert approx >= exact + 40 * n and approx % 256 == 0
+    assert lib.dpc_approx_workspace_bytes(0, 2, 3.0) == 0
+    assert lib.dpc_approx_workspace_bytes(10, 9, 3.0) == 0
+    assert lib.dpc_approx_workspace_bytes(10, 2, -1.0) == 0
