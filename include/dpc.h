@@ -137,6 +137,51 @@ dpc_status dpc_approx_run(const int32_t *pts, int64_t n, int32_t d, double d_cut
                           int64_t *ncenters, uint8_t *approx, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Decision graph (Section 2.1): summaries of the <rho_i, delta_i> pairs from which a
+ * user picks rho_min and delta_min, computed on the device from resident outputs of
+ * dpc_run / dpc_approx_run (rho [n] int32, delta [n] double, device).
+ *
+ * dpc_decision_top: the min(k, m) points of largest delta among the m points with
+ * rho >= rho_min, ordered by delta descending, then id ascending.
+ *   k       1 .. DPC_DECISION_TOP_MAX
+ *   ids     [k] int32 output (device); deltas [k] double output; rhos [k] int32 output
+ *           or NULL; count  device int64 output: the number of entries written
+ *   ws      device workspace of at least DPC_DECISION_WS_BYTES bytes
+ * Errors: DPC_EINVAL (null pointer, n < 1, k out of range), DPC_EWORKSPACE.
+ */
+#define DPC_DECISION_TOP_MAX 4096
+#define DPC_DECISION_WS_BYTES ((size_t)128 << 10)
+dpc_status dpc_decision_top(int64_t n, const int32_t *rho, const double *delta, int32_t rho_min, int32_t k,
+                            int32_t *ids, double *deltas, int32_t *rhos, int64_t *count, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/*
+ * dpc_decision_histogram: counts[i * n_delta_bins + j] (device int64 output, written
+ * whole) = number of points with rho in bin i of rho_edges and delta in bin j of
+ * delta_edges.  Edges are device double arrays of n_bins + 1 increasing values; bins
+ * are half-open [e_k, e_k+1) except the last, which holds its right edge too (an edge
+ * of +inf takes infinite deltas); points outside every bin are not counted.
+ * Errors: DPC_EINVAL (null pointer, n < 1, bins < 1, or more than 2^24 bins in all).
+ */
+dpc_status dpc_decision_histogram(int64_t n, const int32_t *rho, const double *delta, const double *rho_edges,
+                                  int32_t n_rho_bins, const double *delta_edges, int32_t n_delta_bins,
+                                  int64_t *counts, void *stream);
+
+/*
+ * dpc_decision_suggest: a delta_min read off the top list of dpc_decision_top (its
+ * deltas and count, device): among consecutive entries (delta_j, delta_j+1) with
+ * delta_j finite and > d_cut, the pair of largest ratio delta_j / delta_j+1 (a zero
+ * delta_j+1 counts as an infinite ratio; ties: the first pair); delta_min = delta_j,
+ * so that the points singled out by a much longer dependent distance become centers
+ * (Section 2.1, after Def. 5).
+ *   delta_min  device double output: the suggestion, NaN if no pair qualifies
+ *   centers    device int64 output: entries of the list with delta >= delta_min (0 if none)
+ * Errors: DPC_EINVAL (null pointer, d_cut not finite and > 0).
+ */
+dpc_status dpc_decision_suggest(const double *top_deltas, const int64_t *count, double d_cut, double *delta_min,
+                                int64_t *centers, void *stream);
+
+/*
  * dpc_run for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation and outputs as dpc_run, with the scratch space in a static device

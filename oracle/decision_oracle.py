@@ -41,27 +41,26 @@ def top_delta(rho, delta, rho_min: int, k: int):
     return sel.astype(np.int64), delta[sel], rho[sel]
 
 
-def _bin(v, edges):
-    """Index of the bin of v, or -1 (half-open bins, the last one closed)."""
-    nb = len(edges) - 1
-    i = int(np.searchsorted(edges, v, side="right")) - 1
-    if 0 <= i < nb:
-        return i
-    if nb > 0 and v == edges[-1]:
-        return nb - 1
-    return -1
+def _bins(values, edges) -> np.ndarray:
+    """Bin index of each value, -1 outside (half-open bins, the last one closed)."""
+    edges = np.asarray(edges, np.float64)
+    v = np.asarray(values, np.float64)
+    nb = edges.size - 1
+    i = np.searchsorted(edges, v, side="right") - 1
+    i[(i == nb) & (v == edges[-1])] = nb - 1  # the last bin holds its right edge
+    i[(i < 0) | (i >= nb)] = -1
+    return i
 
 
 def histogram(rho, delta, rho_edges, delta_edges) -> np.ndarray:
     """counts[i][j]: points with rho in rho bin i and delta in delta bin j."""
-    rho_edges = np.asarray(rho_edges, np.float64)
-    delta_edges = np.asarray(delta_edges, np.float64)
-    counts = np.zeros((len(rho_edges) - 1, len(delta_edges) - 1), np.int64)
-    for r, dl in zip(np.asarray(rho, np.float64), np.asarray(delta, np.float64)):
-        i, j = _bin(r, rho_edges), _bin(dl, delta_edges)
-        if i >= 0 and j >= 0:
-            counts[i, j] += 1
-    return counts
+    nr, nd = len(rho_edges) - 1, len(delta_edges) - 1
+    a = _bins(rho, rho_edges)
+    b = _bins(delta, delta_edges)
+    ok = (a >= 0) & (b >= 0)
+    counts = np.zeros(nr * nd, np.int64)
+    np.add.at(counts, a[ok] * nd + b[ok], 1)
+    return counts.reshape(nr, nd)
 
 
 def suggest_delta_min(top_deltas, d_cut: float):

@@ -883,6 +883,39 @@ dpc_status dpc_approx_run(const int32_t *pts, int64_t n, int32_t d, double d_cut
   return DPC_OK;
 }
 
+dpc_status dpc_decision_top(int64_t n, const int32_t *rho, const double *delta, int32_t rho_min, int32_t k,
+                            int32_t *ids, double *deltas, int32_t *rhos, int64_t *count, void *ws,
+                            size_t ws_bytes, void *stream) {
+  if (!rho || !delta || !ids || !deltas || !count || !ws) return fail(DPC_EINVAL, "null pointer argument");
+  if (n < 1 || n >= DPC_MAX_POINTS) return fail(DPC_EINVAL, "n must be in [1, 2^27)");
+  if (k < 1 || k > DPC_DECISION_TOP_MAX) return fail(DPC_EINVAL, "k must be in [1, DPC_DECISION_TOP_MAX]");
+  if (ws_bytes < DPC_DECISION_WS_BYTES) return fail(DPC_EWORKSPACE, "workspace smaller than DPC_DECISION_WS_BYTES");
+  hipError_t e = launch_decision_top(n, rho, delta, rho_min, k, ids, deltas, rhos, count, ws,
+                                     static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPC_OK : device_fail(e, "decision top-k kernels");
+}
+
+dpc_status dpc_decision_histogram(int64_t n, const int32_t *rho, const double *delta, const double *rho_edges,
+                                  int32_t n_rho_bins, const double *delta_edges, int32_t n_delta_bins,
+                                  int64_t *counts, void *stream) {
+  if (!rho || !delta || !rho_edges || !delta_edges || !counts) return fail(DPC_EINVAL, "null pointer argument");
+  if (n < 1 || n >= DPC_MAX_POINTS) return fail(DPC_EINVAL, "n must be in [1, 2^27)");
+  if (n_rho_bins < 1 || n_delta_bins < 1 || int64_t(n_rho_bins) * n_delta_bins > (int64_t(1) << 24))
+    return fail(DPC_EINVAL, "bins must be >= 1 on each axis and at most 2^24 in all");
+  hipError_t e = launch_decision_hist(n, rho, delta, rho_edges, n_rho_bins, delta_edges, n_delta_bins, counts,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPC_OK : device_fail(e, "decision histogram kernels");
+}
+
+dpc_status dpc_decision_suggest(const double *top_deltas, const int64_t *count, double d_cut, double *delta_min,
+                                int64_t *centers, void *stream) {
+  if (!top_deltas || !count || !delta_min || !centers) return fail(DPC_EINVAL, "null pointer argument");
+  if (!std::isfinite(d_cut) || !(d_cut > 0.0)) return fail(DPC_EINVAL, "d_cut must be finite and > 0");
+  hipError_t e = launch_decision_suggest(top_deltas, count, d_cut, delta_min, centers,
+                                         static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DPC_OK : device_fail(e, "decision suggestion kernel");
+}
+
 dpc_status dpc_run_static(const int32_t *pts, int64_t n, int32_t d, double d_cut, int32_t rho_min,
                           double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
                           int64_t *ncenters, uint32_t *status, void *stream) {

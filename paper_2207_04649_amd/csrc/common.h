@@ -242,6 +242,16 @@ hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const
                         int32_t rho_min, double delta_min, int32_t *label, int64_t *ncenters,
                         DevHeader *hdr, hipStream_t s);
 hipError_t reset_counters(DevHeader *hdr, bool grid, hipStream_t s);
+// Decision-graph summaries (decision.hip): top-k by delta, <rho, delta> histogram,
+// suggested delta_min.
+hipError_t launch_decision_top(int64_t n, const int32_t *rho, const double *delta, int32_t rho_min, int32_t k,
+                               int32_t *ids, double *deltas, int32_t *rhos, int64_t *count, void *ws,
+                               hipStream_t s);
+hipError_t launch_decision_hist(int64_t n, const int32_t *rho, const double *delta, const double *re, int nr,
+                                const double *de, int nd, int64_t *counts, hipStream_t s);
+hipError_t launch_decision_suggest(const double *top, const int64_t *count, double d_cut, double *delta_min,
+                                   int64_t *centers, hipStream_t s);
+
 // Many-job launches (every phase for all jobs of a BatchMaps, one launch each).
 hipError_t batch_start(const BatchMaps &B, hipStream_t s);
 hipError_t batch_build_grid(const BatchMaps &B, hipStream_t s);

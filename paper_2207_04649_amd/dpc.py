@@ -87,6 +87,9 @@ def lib() -> ctypes.CDLL:
             "dpc_run": (I32, [P, I64, I32, D, I32, D, P, P, P, P, P, P, SZ, P]),
             "dpc_run_static": (I32, [P, I64, I32, D, I32, D, P, P, P, P, P, P, P]),
             "dpc_approx_workspace_bytes": (SZ, [I64, I32, D]),
+            "dpc_decision_top": (I32, [I64, P, P, I32, I32, P, P, P, P, P, SZ, P]),
+            "dpc_decision_histogram": (I32, [I64, P, P, P, I32, P, I32, P, P]),
+            "dpc_decision_suggest": (I32, [P, P, D, P, P, P]),
             "dpc_approx_run": (I32, [P, I64, I32, D, I32, D, P, P, P, P, P, P, P, SZ, P]),
             "dpc_sync_status": (I32, [P, P]),
             "dpc_last_error": (ctypes.c_char_p, []),
@@ -254,6 +257,51 @@ def dpc_approx_run(pts: torch.Tensor, d_cut: float, rho_min: int, delta_min: flo
                                 _ptr(dep), _ptr(delta), _ptr(label), _ptr(ncent), _ptr(approx), _ptr(ws),
                                 ws.numel(), _stream(stream)))
     return out
+
+
+DECISION_TOP_MAX = 4096
+DECISION_WS_BYTES = 128 << 10
+
+
+def dpc_decision_top(rho: torch.Tensor, delta: torch.Tensor, rho_min: int, k: int, ws: torch.Tensor | None = None,
+                     stream=None) -> dict:
+    """The top-k non-noise points by delta (device tensors: ids, deltas, rhos, count)."""
+    n = int(rho.shape[0])
+    _need(rho, torch.int32, (n,), "rho")
+    _need(delta, torch.float64, (n,), "delta")
+    dev = rho.device
+    out = {"ids": torch.empty(k, dtype=torch.int32, device=dev), "deltas": torch.empty(k, dtype=torch.float64, device=dev),
+           "rhos": torch.empty(k, dtype=torch.int32, device=dev), "count": torch.empty(1, dtype=torch.int64, device=dev)}
+    ws = torch.empty(DECISION_WS_BYTES, dtype=torch.uint8, device=dev) if ws is None else ws
+    _check(lib().dpc_decision_top(n, _ptr(rho), _ptr(delta), int(rho_min), int(k), _ptr(out["ids"]),
+                                  _ptr(out["deltas"]), _ptr(out["rhos"]), _ptr(out["count"]), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return out
+
+
+def dpc_decision_histogram(rho: torch.Tensor, delta: torch.Tensor, rho_edges: torch.Tensor,
+                           delta_edges: torch.Tensor, stream=None) -> torch.Tensor:
+    """[n_rho_bins, n_delta_bins] int64 counts of <rho, delta> (device tensors; float64 edges)."""
+    n = int(rho.shape[0])
+    _need(rho, torch.int32, (n,), "rho")
+    _need(delta, torch.float64, (n,), "delta")
+    nr, nd = int(rho_edges.numel()) - 1, int(delta_edges.numel()) - 1
+    _need(rho_edges, torch.float64, (nr + 1,), "rho_edges")
+    _need(delta_edges, torch.float64, (nd + 1,), "delta_edges")
+    counts = torch.empty((max(nr, 0), max(nd, 0)), dtype=torch.int64, device=rho.device)
+    _check(lib().dpc_decision_histogram(n, _ptr(rho), _ptr(delta), _ptr(rho_edges), nr, _ptr(delta_edges), nd,
+                                        _ptr(counts), _stream(stream)))
+    return counts
+
+
+def dpc_decision_suggest(top: dict, d_cut: float, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+    """Suggested delta_min (NaN if none) and its number of centers in the top list."""
+    dev = top["deltas"].device
+    dmin = torch.empty(1, dtype=torch.float64, device=dev)
+    cent = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(lib().dpc_decision_suggest(_ptr(top["deltas"]), _ptr(top["count"]), float(d_cut), _ptr(dmin),
+                                      _ptr(cent), _stream(stream)))
+    return dmin, cent
 
 
 STATIC_SCRATCH_BYTES = 64 << 20

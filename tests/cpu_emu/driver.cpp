@@ -12,6 +12,12 @@
 //
 // With --approx the single record runs through dpc_approx_run instead, and the
 // output ends with the n approx flags (uint8).
+//
+// With --decision the input is int64 n, int32 rho_min, int32 k, double d_cut, int32
+// n_rho_bins, int32 n_delta_bins, then rho[n] (int32), delta[n], rho_edges and
+// delta_edges (doubles); the output is int32 statuses of dpc_decision_top,
+// dpc_decision_suggest and dpc_decision_histogram, int64 count, ids[k], deltas[k],
+// rhos[k], double delta_min, int64 centers, int64 counts[bins].
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -128,7 +134,50 @@ int run_batch(const char *inp, const char *outp, const dpc_tuning *tuning) {
   return 0;
 }
 
+int run_decision(const char *inp, const char *outp) {
+  FILE *in = std::fopen(inp, "rb");
+  if (!in) return 2;
+  int64_t n;
+  int32_t rho_min, k, nr, nd;
+  double d_cut;
+  if (std::fread(&n, 8, 1, in) != 1 || std::fread(&rho_min, 4, 1, in) != 1 || std::fread(&k, 4, 1, in) != 1 ||
+      std::fread(&d_cut, 8, 1, in) != 1 || std::fread(&nr, 4, 1, in) != 1 || std::fread(&nd, 4, 1, in) != 1)
+    return 2;
+  std::vector<int32_t> rho(n);
+  std::vector<double> delta(n), re(nr + 1), de(nd + 1);
+  if (std::fread(rho.data(), 4, n, in) != size_t(n) || std::fread(delta.data(), 8, n, in) != size_t(n) ||
+      std::fread(re.data(), 8, nr + 1, in) != size_t(nr + 1) || std::fread(de.data(), 8, nd + 1, in) != size_t(nd + 1))
+    return 2;
+  std::fclose(in);
+  void *ws = std::aligned_alloc(256, DPC_DECISION_WS_BYTES);
+  std::vector<int32_t> ids(k, -7), rhos(k, -7);
+  std::vector<double> deltas(k, -7.0);
+  std::vector<int64_t> counts(size_t(nr) * nd, -7);
+  int64_t count = -7, centers = -7;
+  double dmin = -7.0;
+  const int32_t s1 = dpc_decision_top(n, rho.data(), delta.data(), rho_min, k, ids.data(), deltas.data(),
+                                      rhos.data(), &count, ws, DPC_DECISION_WS_BYTES, nullptr);
+  const int32_t s2 = dpc_decision_suggest(deltas.data(), &count, d_cut, &dmin, &centers, nullptr);
+  const int32_t s3 = dpc_decision_histogram(n, rho.data(), delta.data(), re.data(), nr, de.data(), nd,
+                                            counts.data(), nullptr);
+  std::free(ws);
+  FILE *out = std::fopen(outp, "wb");
+  std::fwrite(&s1, 4, 1, out);
+  std::fwrite(&s2, 4, 1, out);
+  std::fwrite(&s3, 4, 1, out);
+  std::fwrite(&count, 8, 1, out);
+  std::fwrite(ids.data(), 4, k, out);
+  std::fwrite(deltas.data(), 8, k, out);
+  std::fwrite(rhos.data(), 4, k, out);
+  std::fwrite(&dmin, 8, 1, out);
+  std::fwrite(&centers, 8, 1, out);
+  std::fwrite(counts.data(), 8, counts.size(), out);
+  std::fclose(out);
+  return 0;
+}
+
 int main(int argc, char **argv) {
+  if (argc == 4 && std::string(argv[1]) == "--decision") return run_decision(argv[2], argv[3]);
   bool approx_mode = false;
   if (argc == 4 && std::string(argv[1]) == "--approx") {
     approx_mode = true;

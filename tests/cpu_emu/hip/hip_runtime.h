@@ -289,6 +289,16 @@ inline T emu_readlane(T v, int l) {
 #define __builtin_amdgcn_fence(...) ((void)0)
 inline int __popcll(unsigned long long v) { return __builtin_popcountll(v); }
 inline int __popc(unsigned v) { return __builtin_popcount(v); }
+inline long long __double_as_longlong(double v) {
+  long long r;
+  std::memcpy(&r, &v, 8);
+  return r;
+}
+inline double __longlong_as_double(long long v) {
+  double r;
+  std::memcpy(&r, &v, 8);
+  return r;
+}
 inline int __ffsll(long long v) { return __builtin_ffsll(v); }
 
 template <class T>
