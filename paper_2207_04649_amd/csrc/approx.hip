@@ -173,6 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_ax_near(Plan p, Ws w, ApproxPlan a, 
       const int64_t c0 = row * nc + lo_l;
       const uint32_t j0 = w.cnt[c0], j1 = w.cnt[c0 + (hi_l - lo_l) + 1];
       for (uint32_t j = j0; j < j1; ++j) {
+        // a point of a qualifying cell has a higher density: test that first
+        if (uint32_t(w.sK[j] >> 32) <= rho) continue;
         int64_t d2 = 0;
 #pragma unroll
         for (int t = 0; t < D; ++t) {
