@@ -137,6 +137,30 @@ dpc_status dpc_approx_run(const int32_t *pts, int64_t n, int32_t d, double d_cut
                           int64_t *ncenters, uint8_t *approx, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * S-Approx-DPC (Section 5): one picked point per cell of a grid G' stands for the
+ * cell.  Cells have side Le = 1 + floor(sqrt((Re - 1) / d)), Re = ceil(e^2) for the
+ * double e = eps * d_cut (so a cell's points lie strictly within e of each other);
+ * a cell's pick is its smallest id.
+ *   - a pick gets its exact local density (Def. 1, against all points);
+ *   - a point that was not picked gets dep = its pick, delta = the distance to it,
+ *     and rho = the pick's density (it follows its pick into clusters and noise);
+ *   - first phase: a pick takes the nearest higher-ranked pick among the picks of
+ *     the cells holding a point strictly within d_cut of it (delta <= (1 + eps) d_cut);
+ *   - second phase: a pick with none takes its nearest higher-ranked pick of all
+ *     (+inf and -1 for the top pick).
+ * Ranks are (rho descending, id ascending) over the picks; delta is the correctly
+ * rounded distance.
+ *   eps     (0, 1]
+ *   picked  optional [n] uint8 output (NULL: not written): 1 for the picks
+ *   ws      at least dpc_sapprox_workspace_bytes(n, d, d_cut, eps) bytes (0 if invalid)
+ * Other arguments, outputs and errors as for dpc_run (DPC_EINVAL also for eps out of range).
+ */
+size_t dpc_sapprox_workspace_bytes(int64_t n, int32_t d, double d_cut, double eps);
+dpc_status dpc_sapprox_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, double eps, int32_t rho_min,
+                           double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
+                           int64_t *ncenters, uint8_t *picked, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Decision graph (Section 2.1): summaries of the <rho_i, delta_i> pairs from which a
  * user picks rho_min and delta_min, computed on the device from resident outputs of
  * dpc_run / dpc_approx_run (rho [n] int32, delta [n] double, device).

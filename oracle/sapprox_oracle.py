@@ -23,8 +23,8 @@ Steps, in the section's order:
 Readings where the section leaves a choice (each is also in the design notes):
 
 * integer coordinates: the cell side is Le = 1 + floor(sqrt((Re - 1) / d)) with
-  Re = ceil((eps d_cut)^2), so two points of one cell lie strictly within
-  eps * d_cut; the cell of a point is (x_1 // Le, ..., x_d // Le);
+  Re = ceil(e^2), e = eps * d_cut as a double product, so two points of one cell
+  lie strictly within e; the cell of a point is (x_1 // Le, ..., x_d // Le);
 * the pick of a cell is its smallest id;
 * "higher local density" is the exact method's rank order (rho descending, id
   ascending) over the picks;
@@ -38,17 +38,16 @@ Readings where the section leaves a choice (each is also in the design notes):
 from __future__ import annotations
 
 import math
-from fractions import Fraction
-
 import numpy as np
 
 from . import dpc_oracle
 
 
 def eps_cutoff_square(d_cut: float, eps: float) -> int:
-    """Re = ceil((eps d_cut)^2), exact (eps and d_cut as the doubles given)."""
-    f = Fraction(eps) * Fraction(d_cut)
-    return max(1, math.ceil(f * f))
+    """Re = ceil(e^2) for e = eps * d_cut rounded to a double (one IEEE product),
+    exact as for d_cut; 1 if the product underflows to zero."""
+    e = float(eps) * float(d_cut)
+    return dpc_oracle.cutoff_square(e) if e > 0.0 else 1
 
 
 def cell_side(Re: int, d: int) -> int:

@@ -582,6 +582,37 @@ ApproxPlan make_approx_plan(const Plan &p, double d_cut) {
   return a;
 }
 
+// ceil(e^2) for e = eps * d_cut rounded to a double (one IEEE product), exactly as
+// for d_cut itself; 1 when the product underflows to zero.
+int64_t eps_cutoff_square(double d_cut, double eps) {
+  const double e = eps * d_cut;
+  return e > 0.0 ? cutoff_square(e) : 1;
+}
+
+SApproxPlan make_sapprox_plan(const Plan &p, double d_cut, double eps) {
+  SApproxPlan a{};
+  const int64_t Re = eps_cutoff_square(d_cut, eps);
+  a.Le = int32_t(1 + isqrt64((Re - 1) / p.d));
+  uint64_t slots = 256;
+  while (slots < 2 * uint64_t(p.n)) slots <<= 1;
+  a.mask = uint32_t(slots - 1);
+  size_t o = align_up(p.total);
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  a.o_cnt = take(256);
+  a.o_rep = take(slots * 4);
+  a.o_pick = take(slots * 4);
+  a.o_ppos = take(slots * 4);
+  a.o_prho = take(slots * 4);
+  a.o_ent = take(size_t(p.n) * 4);
+  a.o_plist = take(size_t(p.n) * 4);
+  a.total = o;
+  return a;
+}
+
 }  // namespace dpc
 
 using namespace dpc;
@@ -877,6 +908,40 @@ dpc_status dpc_approx_run(const int32_t *pts, int64_t n, int32_t d, double d_cut
   }
   if ((e = launch_approx(p, w, a, ws, dep, delta, rho, approx, s)) != hipSuccess)
     return device_fail(e, "approximate dependent kernels");
+  ProfScope ps(s, kProfLabel);
+  e = launch_label(n, rho, dep, delta, rho_min, delta_min, label, ncenters, w.hdr, s);
+  if (e != hipSuccess) return device_fail(e, "label kernels");
+  return DPC_OK;
+}
+
+size_t dpc_sapprox_workspace_bytes(int64_t n, int32_t d, double d_cut, double eps) {
+  Plan p;
+  if (!(eps > 0.0 && eps <= 1.0)) return 0;
+  return make_plan(n, d, d_cut, nullptr, &p) ? make_sapprox_plan(p, d_cut, eps).total : 0;
+}
+
+dpc_status dpc_sapprox_run(const int32_t *pts, int64_t n, int32_t d, double d_cut, double eps, int32_t rho_min,
+                           double delta_min, int32_t *rho, int32_t *dep, double *delta, int32_t *label,
+                           int64_t *ncenters, uint8_t *picked, void *ws, size_t ws_bytes, void *stream) {
+  Plan p;
+  dpc_status st = check_common(pts, n, d, d_cut, ws, ws_bytes, &p);
+  if (st != DPC_OK) return st;
+  if (!(eps > 0.0 && eps <= 1.0)) return fail(DPC_EINVAL, "eps must be in (0, 1]");
+  const SApproxPlan a = make_sapprox_plan(p, d_cut, eps);
+  if (ws_bytes < a.total) return fail(DPC_EWORKSPACE, "workspace smaller than dpc_sapprox_workspace_bytes()");
+  if (!rho || !dep || !delta || !label || !ncenters) return fail(DPC_EINVAL, "null pointer argument");
+  if (rho_min < 0) return fail(DPC_EINVAL, "rho_min must be >= 0");
+  if (std::isnan(delta_min) || !(delta_min > d_cut)) return fail(DPC_EINVAL, "delta_min must exceed d_cut");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Ws w = resolve(p, ws);
+  hipError_t e = clear_status(w.hdr, s);
+  if (e != hipSuccess) return device_fail(e, "status reset");
+  {
+    ProfScope ps(s, kProfGrid);
+    if ((e = build_grid(p, w, pts, grid_stamp(p, pts), s)) != hipSuccess) return device_fail(e, "grid build");
+  }
+  if ((e = launch_sapprox(p, w, a, ws, dep, delta, rho, picked, s)) != hipSuccess)
+    return device_fail(e, "S-Approx-DPC kernels");
   ProfScope ps(s, kProfLabel);
   e = launch_label(n, rho, dep, delta, rho_min, delta_min, label, ncenters, w.hdr, s);
   if (e != hipSuccess) return device_fail(e, "label kernels");

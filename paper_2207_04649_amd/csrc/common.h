@@ -106,6 +106,14 @@ struct ApproxPlan {
   size_t o_cnt, o_rep, o_top, o_minrho, o_ent, o_plist, total;
 };
 
+// S-Approx-DPC's grid G' (cells of side Le) and its part of the workspace, which
+// follows the exact path's.
+struct SApproxPlan {
+  int32_t Le;        // cell side: 1 + floor(sqrt((Re - 1) / d)), Re = ceil((eps d_cut)^2)
+  uint32_t mask;     // hash table slots - 1 (slots: a power of two >= 2n)
+  size_t o_cnt, o_rep, o_pick, o_ppos, o_prho, o_ent, o_plist, total;
+};
+
 // Pointers into one workspace, resolved from a Plan.
 struct Ws {
   DevHeader *hdr;
@@ -238,6 +246,10 @@ hipError_t launch_exact_remainder(const Plan &p, const Ws &w, hipStream_t s);
 // in id order (approx, if not null, gets 1 where the dependent point is approximate).
 hipError_t launch_approx(const Plan &p, const Ws &w, const ApproxPlan &a, void *base, int32_t *dep,
                          double *delta, int32_t *rho, uint8_t *approx, hipStream_t s);
+// S-Approx-DPC after the grid build: G', the picks' densities, both phases, the
+// outputs in id order (picked, if not null, gets 1 for the picked points).
+hipError_t launch_sapprox(const Plan &p, const Ws &w, const SApproxPlan &a, void *base, int32_t *dep,
+                          double *delta, int32_t *rho, uint8_t *picked, hipStream_t s);
 hipError_t launch_label(int64_t n, const int32_t *rho, const int32_t *dep, const double *delta,
                         int32_t rho_min, double delta_min, int32_t *label, int64_t *ncenters,
                         DevHeader *hdr, hipStream_t s);

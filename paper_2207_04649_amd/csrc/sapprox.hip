@@ -1,0 +1,315 @@
+// S-Approx-DPC (Section 5): one picked point per cell of a grid G' of side about
+// eps * d_cut / sqrt(d) stands for its cell.
+//
+//   * G' is an open-addressing hash table over the occupied cells (as in
+//     Approx-DPC); integer side Le = 1 + floor(sqrt((Re - 1) / d)), Re =
+//     ceil((eps d_cut)^2), so the points of a cell lie strictly within eps * d_cut
+//     of each other.  A cell's pick is its smallest id (one atomicMin per point).
+//   * Local density of the picks only (Def. 1, against all points): one lane per
+//     pick, a range search of radius d_cut over the exact grid's rows.
+//   * A point that was not picked takes its cell's pick (true distance, below
+//     eps * d_cut) and reports the pick's density.
+//   * First phase: a pick takes the nearest higher-ranked pick among the picks of
+//     the cells that hold a point strictly within d_cut of it (N(c)).
+//   * Second phase: the picks left take their nearest higher-ranked pick through
+//     the exact path's ring search and prefix scan.  Their rank keys rank every
+//     pick above every other point (a point that was not picked gets density key
+//     1, a pick its density plus one when that stays within n, else its density:
+//     a pick of density n is within d_cut of every point, so then no pick has
+//     density 1), so that search only ever returns picks.  The section's
+//     temporary clusters prune this same search; its result does not depend on
+//     them.
+#include "common.h"
+#include "prof.h"
+
+namespace dpc {
+namespace {
+
+constexpr uint32_t kEmpty = 0xffffffffu;
+
+struct SaWs {
+  uint32_t *cnt;    // [4] counters: picks, largest pick density, first-phase picks
+  uint32_t *rep;    // [slots] cell-order position of the point that opened the slot, kEmpty if free
+  uint32_t *pick;   // [slots] smallest id of the cell (its pick), kEmpty before any point
+  uint32_t *ppos;   // [slots] cell-order position of the pick
+  uint32_t *prho;   // [slots] density of the pick
+  uint32_t *ent;    // [n] table slot of each cell-order position
+  uint32_t *plist;  // [n] cell-order positions of the picks
+};
+
+SaWs sa_resolve(const SApproxPlan &a, void *base) {
+  char *b = static_cast<char *>(base);
+  SaWs x;
+  x.cnt = reinterpret_cast<uint32_t *>(b + a.o_cnt);
+  x.rep = reinterpret_cast<uint32_t *>(b + a.o_rep);
+  x.pick = reinterpret_cast<uint32_t *>(b + a.o_pick);
+  x.ppos = reinterpret_cast<uint32_t *>(b + a.o_ppos);
+  x.prho = reinterpret_cast<uint32_t *>(b + a.o_prho);
+  x.ent = reinterpret_cast<uint32_t *>(b + a.o_ent);
+  x.plist = reinterpret_cast<uint32_t *>(b + a.o_plist);
+  return x;
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t cell_hash(const int32_t *c) {
+  uint64_t h = 0x9E3779B97F4A7C15ull;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    h = (h ^ uint32_t(c[t])) * 0xFF51AFD7ED558CCDull;
+    h ^= h >> 29;
+  }
+  return uint32_t(h ^ (h >> 32));
+}
+
+// One atomic per wave; every lane of the wave calls it.
+__device__ __forceinline__ void wave_push(uint32_t *counter, uint32_t *list, bool take, uint32_t q) {
+  const uint64_t m = __ballot(take);
+  const int lane = lane_id();
+  uint32_t base = 0;
+  if (lane == 0 && m != 0) base = atomicAdd(counter, uint32_t(__popcll(m)));
+  base = __shfl(base, 0, kWave);
+  if (take) list[base + uint32_t(__popcll(m & ((uint64_t(1) << lane) - 1)))] = q;
+}
+
+template <int D>
+__device__ __forceinline__ int64_t d2_of(const int32_t *__restrict__ spts, uint32_t a, const int32_t *xq) {
+  int64_t s = 0;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    const int64_t df = int64_t(spts[int64_t(a) * D + t]) - xq[t];
+    s += df * df;
+  }
+  return s;
+}
+
+// Visits every cell-order position j of the exact grid's rows that can hold a
+// point within d_cut of xq (the box of radius floor(sqrt(R - 1)) over the first gm
+// coordinates; its cells along the last grid dimension are one run of positions).
+template <int D, class F>
+__device__ __forceinline__ void for_each_near(const Plan &p, const Ws &w, const int32_t *xq, F &&f) {
+  const int32_t L = p.L, nc = p.nc, gm = p.gm, r0 = p.L0;
+  const int last = gm - 1;
+  int32_t lo[D], hi[D], cur[D];
+  int32_t lo_l = 0, hi_l = 0;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    lo[t] = t < gm ? max(xq[t] - r0, 0) / L : 0;
+    hi[t] = t < gm ? min(xq[t] + r0, DPC_COORD_LIMIT - 1) / L : 0;
+    cur[t] = lo[t];
+    if (t == last) {
+      lo_l = lo[t];
+      hi_l = hi[t];
+    }
+  }
+  for (;;) {
+    int64_t row = 0;
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+      if (t < last) row = row * nc + cur[t];
+    const int64_t c0 = row * nc + lo_l;
+    const uint32_t j0 = w.cnt[c0], j1 = w.cnt[c0 + (hi_l - lo_l) + 1];
+    for (uint32_t j = j0; j < j1; ++j) f(j);
+    bool carry = true;
+#pragma unroll
+    for (int t = D - 1; t >= 0; --t) {
+      if (t < last && carry) {
+        if (cur[t] < hi[t]) {
+          ++cur[t];
+          carry = false;
+        } else {
+          cur[t] = lo[t];
+        }
+      }
+    }
+    if (carry) break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sa_clear(SaWs x, uint32_t slots) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < 4) x.cnt[i] = 0;
+  if (i < slots) {
+    x.rep[i] = kEmpty;
+    x.pick[i] = kEmpty;
+  }
+}
+
+// Each point finds (or opens) its cell's slot and lowers the slot's pick id.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sa_insert(Plan p, Ws w, SApproxPlan a, SaWs x) {
+  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= p.n || grid_skipped(w.hdr)) return;
+  int32_t c[D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) c[t] = w.spts[q * D + t] / a.Le;
+  uint32_t h = cell_hash<D>(c) & a.mask;
+  for (uint32_t probe = 0; probe <= a.mask; ++probe) {
+    uint32_t r = x.rep[h];
+    if (r == kEmpty) {
+      r = atomicCAS(&x.rep[h], kEmpty, uint32_t(q));
+      if (r == kEmpty) break;
+    }
+    bool same = true;
+#pragma unroll
+    for (int t = 0; t < D; ++t) same = same && w.spts[int64_t(r) * D + t] / a.Le == c[t];
+    if (same) break;
+    h = (h + 1) & a.mask;
+  }
+  x.ent[q] = h;
+  atomicMin(&x.pick[h], uint32_t(w.sid[q]));
+}
+
+// The picks: their positions per slot and as a list.
+__global__ __launch_bounds__(kBlock) void k_sa_split(Plan p, Ws w, SaWs x) {
+  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (grid_skipped(w.hdr)) return;
+  bool star = false;
+  if (q < p.n) {
+    const uint32_t e = x.ent[q];
+    star = x.pick[e] == uint32_t(w.sid[q]);
+    if (star) x.ppos[e] = uint32_t(q);
+  }
+  wave_push(&x.cnt[0], x.plist, star, uint32_t(q));
+}
+
+// Local density of each pick (Def. 1 against every point).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sa_density(Plan p, Ws w, SaWs x) {
+  if (grid_skipped(w.hdr)) return;
+  const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
+  if (u >= x.cnt[0]) return;
+  const uint32_t q = x.plist[u];
+  int32_t xq[D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) xq[t] = w.spts[int64_t(q) * D + t];
+  uint32_t rho = 0;
+  for_each_near<D>(p, w, xq, [&](uint32_t j) { rho += d2_of<D>(w.spts, j, xq) < p.R ? 1u : 0u; });
+  x.prho[x.ent[q]] = rho;
+  atomicMax(&x.cnt[1], rho);
+}
+
+// Rank keys: every pick above every other point (see the file comment), and the
+// dependent point of each point that was not picked: its cell's pick.
+__global__ __launch_bounds__(kBlock) void k_sa_keys(Plan p, Ws w, SaWs x) {
+  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= p.n || grid_skipped(w.hdr)) return;
+  const uint32_t e = x.ent[q];
+  const uint32_t id = uint32_t(w.sid[q]);
+  const uint32_t shift = uint64_t(x.cnt[1]) < uint64_t(p.n) ? 1u : 0u;
+  const uint32_t pp = x.ppos[e];
+  const bool star = pp == uint32_t(q);
+  const uint64_t r = star ? uint64_t(x.prho[e]) + shift : 1u;
+  const uint64_t key = (r << 32) | uint32_t(~id);
+  w.sK[q] = key;
+  if (w.srec) {  // the ring search's packed records carry the rank key
+    const uint32_t a0 = w.spk[q * p.words], a1 = p.words == 2 ? w.spk[q * p.words + 1] : 0u;
+    w.srec[q] = make_uint4(a0, a1, uint32_t(key), uint32_t(key >> 32));
+  }
+  if (!star) {
+    int64_t s = 0;
+    for (int t = 0; t < p.d; ++t) {
+      const int64_t df = int64_t(w.spts[q * p.d + t]) - w.spts[int64_t(pp) * p.d + t];
+      s += df * df;
+    }
+    w.best[q] = (uint64_t(s) << kIdBits) | x.pick[e];
+  }
+}
+
+// First phase, one lane per pick: the nearest higher-ranked pick of the cells
+// that hold a point strictly within d_cut; picks without one go to the ring
+// search's list with no key.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sa_phase1(Plan p, Ws w, SaWs x) {
+  if (grid_skipped(w.hdr)) return;
+  const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
+  const bool own = u < x.cnt[0];
+  const uint32_t q = own ? x.plist[u] : 0u;
+  uint64_t best = kNoKey;
+  if (own) {
+    int32_t xq[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) xq[t] = w.spts[int64_t(q) * D + t];
+    const uint32_t e = x.ent[q];
+    const uint32_t rho = x.prho[e], id = uint32_t(w.sid[q]);
+    uint32_t last_e = e;  // consecutive positions often share a cell
+    for_each_near<D>(p, w, xq, [&](uint32_t j) {
+      const uint32_t e2 = x.ent[j];
+      if (e2 == e || e2 == last_e) return;
+      if (d2_of<D>(w.spts, j, xq) >= p.R) return;
+      last_e = e2;
+      const uint32_t r2 = x.prho[e2], id2 = x.pick[e2];
+      if (!(r2 > rho || (r2 == rho && id2 < id))) return;
+      const uint64_t key = (uint64_t(d2_of<D>(w.spts, x.ppos[e2], xq)) << kIdBits) | id2;
+      best = key < best ? key : best;
+    });
+    w.best[q] = best;
+  }
+  wave_push(&w.hdr->n_unres, w.unres, own && best == kNoKey, q);
+  const uint64_t m = __ballot(own && best != kNoKey);
+  if (lane_id() == 0 && m != 0) atomicAdd(&x.cnt[2], uint32_t(__popcll(m)));
+}
+
+// Outputs in id order: dep and the true distance from the key, the pick's density,
+// the picked flag.
+__global__ __launch_bounds__(kBlock) void k_sa_finish(Plan p, Ws w, SaWs x, int32_t *__restrict__ dep,
+                                                      double *__restrict__ delta, int32_t *__restrict__ rho,
+                                                      uint8_t *__restrict__ picked) {
+  if (grid_skipped(w.hdr)) return;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= p.n) return;
+  const uint32_t q = w.key[i];
+  const uint64_t key = w.best[q];
+  if (key == kNoKey) {
+    dep[i] = -1;
+    delta[i] = __builtin_huge_val();
+  } else {
+    dep[i] = int32_t(key & kIdMask);
+    delta[i] = __builtin_sqrt(double(key >> kIdBits));  // correctly rounded (IEEE sqrt)
+  }
+  const uint32_t e = x.ent[q];
+  rho[i] = int32_t(x.prho[e]);
+  if (picked) picked[i] = x.ppos[e] == q ? 1 : 0;
+}
+
+template <int D>
+void launch_sa_d(const Plan &p, const Ws &w, const SApproxPlan &a, const SaWs &x, hipStream_t s) {
+  DPC_LAUNCH((k_sa_insert<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
+  DPC_LAUNCH((k_sa_split), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+  DPC_LAUNCH((k_sa_density<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+  DPC_LAUNCH((k_sa_keys), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+  DPC_LAUNCH((k_sa_phase1<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+}
+
+}  // namespace
+
+hipError_t launch_sapprox(const Plan &p, const Ws &w, const SApproxPlan &a, void *base, int32_t *dep,
+                          double *delta, int32_t *rho, uint8_t *picked, hipStream_t s) {
+  const SaWs x = sa_resolve(a, base);
+  hipError_t e;
+  {
+    ProfScope ps(s, kProfApprox);
+    DPC_LAUNCH((k_sa_clear), blocks_for(int64_t(a.mask) + 1, kBlock), kBlock, s, x, a.mask + 1);
+    switch (p.d) {
+      case 1: launch_sa_d<1>(p, w, a, x, s); break;
+      case 2: launch_sa_d<2>(p, w, a, x, s); break;
+      case 3: launch_sa_d<3>(p, w, a, x, s); break;
+      case 4: launch_sa_d<4>(p, w, a, x, s); break;
+      case 5: launch_sa_d<5>(p, w, a, x, s); break;
+      case 6: launch_sa_d<6>(p, w, a, x, s); break;
+      case 7: launch_sa_d<7>(p, w, a, x, s); break;
+      case 8: launch_sa_d<8>(p, w, a, x, s); break;
+      default: return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    ProfScope ps(s, kProfRankSort);
+    if ((e = rank_sort(p, w, s)) != hipSuccess) return e;
+  }
+  if ((e = launch_exact_remainder(p, w, s)) != hipSuccess) return e;
+  ProfScope ps(s, kProfFinish);
+  DPC_LAUNCH((k_sa_finish), blocks_for(p.n, kBlock), kBlock, s, p, w, x, dep, delta, rho, picked);
+  return hipGetLastError();
+}
+
+}  // namespace dpc

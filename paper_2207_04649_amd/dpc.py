@@ -87,6 +87,8 @@ def lib() -> ctypes.CDLL:
             "dpc_run": (I32, [P, I64, I32, D, I32, D, P, P, P, P, P, P, SZ, P]),
             "dpc_run_static": (I32, [P, I64, I32, D, I32, D, P, P, P, P, P, P, P]),
             "dpc_approx_workspace_bytes": (SZ, [I64, I32, D]),
+            "dpc_sapprox_workspace_bytes": (SZ, [I64, I32, D, D]),
+            "dpc_sapprox_run": (I32, [P, I64, I32, D, D, I32, D, P, P, P, P, P, P, P, SZ, P]),
             "dpc_decision_top": (I32, [I64, P, P, I32, I32, P, P, P, P, P, SZ, P]),
             "dpc_decision_histogram": (I32, [I64, P, P, P, I32, P, I32, P, P]),
             "dpc_decision_suggest": (I32, [P, P, D, P, P, P]),
@@ -256,6 +258,33 @@ def dpc_approx_run(pts: torch.Tensor, d_cut: float, rho_min: int, delta_min: flo
     _check(lib().dpc_approx_run(_ptr(pts), n, d, float(d_cut), int(rho_min), float(delta_min), _ptr(rho),
                                 _ptr(dep), _ptr(delta), _ptr(label), _ptr(ncent), _ptr(approx), _ptr(ws),
                                 ws.numel(), _stream(stream)))
+    return out
+
+
+def dpc_sapprox_workspace_bytes(n: int, d: int, d_cut: float, eps: float) -> int:
+    return int(lib().dpc_sapprox_workspace_bytes(int(n), int(d), float(d_cut), float(eps)))
+
+
+def dpc_sapprox_run(pts: torch.Tensor, d_cut: float, eps: float, rho_min: int, delta_min: float,
+                    ws: torch.Tensor | None = None, out: dict | None = None, stream=None) -> dict:
+    """S-Approx-DPC: rho, dep, delta, label, ncenters and the picked flags (device tensors)."""
+    n, d = _pts(pts)
+    dev = pts.device
+    out = out if out is not None else {}
+    rho = out.setdefault("rho", torch.empty(n, dtype=torch.int32, device=dev))
+    dep = out.setdefault("dep", torch.empty(n, dtype=torch.int32, device=dev))
+    delta = out.setdefault("delta", torch.empty(n, dtype=torch.float64, device=dev))
+    label = out.setdefault("label", torch.empty(n, dtype=torch.int32, device=dev))
+    ncent = out.setdefault("ncenters", torch.empty(1, dtype=torch.int64, device=dev))
+    picked = out.setdefault("picked", torch.empty(n, dtype=torch.uint8, device=dev))
+    if ws is None:
+        nb = dpc_sapprox_workspace_bytes(n, d, d_cut, eps)
+        if nb == 0:
+            raise DpcError(DPC_EINVAL, "no plan for these sizes")
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(lib().dpc_sapprox_run(_ptr(pts), n, d, float(d_cut), float(eps), int(rho_min), float(delta_min),
+                                 _ptr(rho), _ptr(dep), _ptr(delta), _ptr(label), _ptr(ncent), _ptr(picked),
+                                 _ptr(ws), ws.numel(), _stream(stream)))
     return out
 
 

@@ -13,6 +13,9 @@
 // With --approx the single record runs through dpc_approx_run instead, and the
 // output ends with the n approx flags (uint8).
 //
+// With --sapprox EPS the single record runs through dpc_sapprox_run with that eps,
+// and the output ends with the n picked flags (uint8).
+//
 // With --decision the input is int64 n, int32 rho_min, int32 k, double d_cut, int32
 // n_rho_bins, int32 n_delta_bins, then rho[n] (int32), delta[n], rho_edges and
 // delta_edges (doubles); the output is int32 statuses of dpc_decision_top,
@@ -178,11 +181,18 @@ int run_decision(const char *inp, const char *outp) {
 
 int main(int argc, char **argv) {
   if (argc == 4 && std::string(argv[1]) == "--decision") return run_decision(argv[2], argv[3]);
-  bool approx_mode = false;
+  bool approx_mode = false, sapprox_mode = false;
+  double eps = 0.0;
   if (argc == 4 && std::string(argv[1]) == "--approx") {
     approx_mode = true;
     argv[1] = argv[2];
     argv[2] = argv[3];
+    argc = 3;
+  } else if (argc == 5 && std::string(argv[1]) == "--sapprox") {
+    sapprox_mode = true;
+    eps = std::atof(argv[2]);
+    argv[1] = argv[3];
+    argv[2] = argv[4];
     argc = 3;
   }
   if (argc == 4 && std::string(argv[1]) == "--batch") return run_batch(argv[2], argv[3], nullptr);
@@ -209,17 +219,21 @@ int main(int argc, char **argv) {
   std::vector<int32_t> pts(size_t(n) * d);
   if (std::fread(pts.data(), 4, pts.size(), in) != pts.size()) return 2;
   std::fclose(in);
-  const size_t wsb = approx_mode ? dpc_approx_workspace_bytes(n, d, d_cut) : dpc_workspace_bytes(n, d, d_cut);
+  const size_t wsb = approx_mode    ? dpc_approx_workspace_bytes(n, d, d_cut)
+                     : sapprox_mode ? dpc_sapprox_workspace_bytes(n, d, d_cut, eps)
+                                    : dpc_workspace_bytes(n, d, d_cut);
   void *ws = std::aligned_alloc(256, (wsb + 255) / 256 * 256);
   std::vector<int32_t> rho(n), dep(n), label(n);
   std::vector<double> delta(n);
   std::vector<uint8_t> approx(n, 2);
   int64_t ncenters = -1;
-  const int32_t st = approx_mode
-                         ? dpc_approx_run(pts.data(), n, d, d_cut, rho_min, delta_min, rho.data(), dep.data(),
-                                          delta.data(), label.data(), &ncenters, approx.data(), ws, wsb, nullptr)
-                         : dpc_run(pts.data(), n, d, d_cut, rho_min, delta_min, rho.data(), dep.data(),
-                                   delta.data(), label.data(), &ncenters, ws, wsb, nullptr);
+  const int32_t st =
+      approx_mode    ? dpc_approx_run(pts.data(), n, d, d_cut, rho_min, delta_min, rho.data(), dep.data(),
+                                      delta.data(), label.data(), &ncenters, approx.data(), ws, wsb, nullptr)
+      : sapprox_mode ? dpc_sapprox_run(pts.data(), n, d, d_cut, eps, rho_min, delta_min, rho.data(), dep.data(),
+                                       delta.data(), label.data(), &ncenters, approx.data(), ws, wsb, nullptr)
+                     : dpc_run(pts.data(), n, d, d_cut, rho_min, delta_min, rho.data(), dep.data(), delta.data(),
+                               label.data(), &ncenters, ws, wsb, nullptr);
   const int32_t st2 = dpc_sync_status(ws, nullptr);
   std::free(ws);
   FILE *out = std::fopen(argv[2], "wb");
@@ -230,7 +244,7 @@ int main(int argc, char **argv) {
   std::fwrite(dep.data(), 4, n, out);
   std::fwrite(delta.data(), 8, n, out);
   std::fwrite(label.data(), 4, n, out);
-  if (approx_mode) std::fwrite(approx.data(), 1, n, out);
+  if (approx_mode || sapprox_mode) std::fwrite(approx.data(), 1, n, out);
   std::fclose(out);
   return 0;
 }
