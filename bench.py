@@ -56,9 +56,16 @@ def rooflines(job, per_ms: dict, sum_rho: int, work: dict, plan: dict) -> dict:
 
     * density (ALU): the algorithmic work is sum(rho), the in-ball tests no exact
       method can skip (Def. 1), each at test_ops(d);
-    * search, ringk, peaks (ALU): the candidate tests each makes (counted by the
-      kernels in an instrumented call), at test_ops(d): the pairs of a point and a
-      point of higher rank in its searched cells (Defs. 2-3);
+    * search, peaks (ALU): the candidate tests each makes (counted by the kernels
+      in an instrumented call), at test_ops(d): the pairs of a point and a point of
+      higher rank in its searched cells (Defs. 2-3);
+    * ringk (HBM): its candidates are scattered records (one wave per point reads
+      the cells of a sparse annulus), so the bound is memory; the algorithmic
+      bytes are the candidate records it must read, tests x record size (16-byte
+      packed records in lane form with packed coordinates, else the rank key
+      and the coordinate row);
+    * finish (HBM): per point the cell-order position, best key and rank key
+      read, dep, delta and rho written (36 bytes);
     * grid_build (HBM): grid_bytes() against 8 TB/s.
     """
     ops = test_ops(job.d)
@@ -75,8 +82,21 @@ def rooflines(job, per_ms: dict, sum_rho: int, work: dict, plan: dict) -> dict:
 
     alu("density", sum_rho, "sum of rho (in-ball pairs, self included)")
     alu("search", work.get("tests_search", 0), "candidate tests of the window search")
-    alu("ringk", work.get("tests_ring", 0), "candidate tests of the ring search")
     alu("peaks", work.get("tests_peaks", 0), "candidate tests of the prefix scan")
+
+    def hbm(name, nbytes, algorithmic):
+        t = per_ms.get(name)
+        if not t:
+            return
+        a = nbytes / (t * 1e-3) / 1e9
+        out[name] = {"avg_ms": t, "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": a / HBM_PEAK_GBS, "traffic": kernel_traffic(name, job.name),
+                     "bytes_per_launch": nbytes, "work": algorithmic}
+
+    packed = plan.get("lanes") and job.d <= 4 and plan.get("mode") == 0
+    rec = 16 if packed else 8 + 4 * job.d
+    hbm("ringk", work.get("tests_ring", 0) * rec, f"candidate records read ({rec} bytes per test)")
+    hbm("finish", 36 * job.n, "36 bytes per point (position, best key, rank key in; dep, delta, rho out)")
     t = per_ms.get("grid_build")
     if t:
         b = grid_bytes(job.n, job.d, plan["cells"])
@@ -109,7 +129,13 @@ GROUP_KERNELS = {
     "finish": ("k_finish",),
     "label": ("k_label_init", "k_jump", "k_root"),
 }
-HBM_BYTES: dict = {}  # {workload: {"source": hash, group: bytes per launch}}
+# walks_4m_d4: the counters of profiles/hbm_counters_walks_4m_d4.txt (groups whose
+# kernels run only in them; k_jump runs 3 times per step).
+HBM_BYTES: dict = {  # {workload: {"source": hash, group: bytes per launch}}
+    "walks_4m_d4": {"source": "b53d3edb1ee348d3", "ringk": 4757.3e6, "search": (1057.6 + 5.0) * 1e6,
+                    "density": 890.4e6, "finish": 1044.1e6, "peaks": (45.9 + 42.6) * 1e6,
+                    "label": (40.8 + 3 * 18.4 + 17.8) * 1e6},
+}
 
 
 def source_hash(files) -> str:
@@ -185,8 +211,12 @@ def make_serve_requests(duration: float):
     trace = inputs.serve_trace(duration=duration)
     specs = [r.spec for r in trace if r.kind == "new"]
     workers = max(1, min(16, os.cpu_count() or 1))
+    jobs = {}
     with cf.ProcessPoolExecutor(workers) as ex:
-        jobs = dict(zip((sp.seed for sp in specs), ex.map(_make_job, specs, chunksize=4)))
+        for k, (sp, job) in enumerate(zip(specs, ex.map(_make_job, specs, chunksize=4))):
+            jobs[sp.seed] = job
+            if (k + 1) % 1000 == 0:
+                print(f"serve: {k + 1} of {len(specs)} new jobs drawn", file=sys.stderr, flush=True)
     return serve.trace_requests(trace, lambda spec: jobs[spec.seed])
 
 
@@ -204,11 +234,20 @@ def bench_serve(args, reqs) -> int:
     dpc.dpc_run(t, warm.d_cut, warm.rho_min, warm.delta_min)
     torch.cuda.synchronize()
     results = {}
-    for name, slots, group in (("continuous", args.slots, True), ("one_slot_fifo", 1, False)):
+    # continuous: `slots` streams for new jobs (small ones grouped) and one of its own for
+    # re-thresholds; the comparison: one stream, every request in arrival order
+    for name, slots, group, relabel in (("continuous", args.slots, True, 1), ("one_slot_fifo", 1, False, 0)):
         rq = [copy.copy(q) for q in reqs]
-        srv = serve.Server(budget_bytes=64 << 30, slots=slots, group_small=group)
+        srv = serve.Server(budget_bytes=64 << 30, slots=slots, group_small=group, relabel_slots=relabel)
         t0 = time.perf_counter()
-        srv.run(rq)
+        def progress(k, n, name=name, srv=srv, t0=t0):
+            staged = sum(b.numel() for b in srv.stage_in + srv.stage_out if b is not None)
+            with open("/proc/self/statm") as f:
+                rss = int(f.read().split()[1]) * os.sysconf("SC_PAGE_SIZE")
+            print(f"{name}: {k} of {n} requests done, {time.perf_counter() - t0:.1f} s, pinned staging "
+                  f"{staged / 2 ** 20:.0f} MiB, host RSS {rss / 2 ** 30:.2f} GiB", file=sys.stderr, flush=True)
+
+        srv.run(rq, progress=progress)
         wall = time.perf_counter() - t0
         done = [q for q in rq if not q.dropped]
         results[name] = {"latency": serve.latency_summary(rq), "wall_s": wall,
@@ -233,7 +272,7 @@ def bench_serve(args, reqs) -> int:
         "config": {"workload": "serve", "duration_s": args.duration, "rate_per_s": 200.0,
                    "requests": len(reqs), "new": sum(1 for q in reqs if q.kind == "new"),
                    "rethreshold": sum(1 for q in reqs if q.kind == "rethreshold"), "slots": args.slots,
-                   "hbm_budget_gb": 64},
+                   "relabel_slots": 1, "hbm_budget_gb": 64},
         "latency": main_r["latency"],
         "requests_per_s": main_r["requests_per_s"],
         "new_points_per_s": main_r["new_points_per_s"],
@@ -354,9 +393,13 @@ def main() -> int:
     ap.add_argument("--extra", default="blobs_1m_d2", help="a second workload measured as an extra key ('' for none)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-approx", action="store_true", help="skip the Approx-DPC lines")
+    ap.add_argument("--approx-only", action="store_true", help="time Approx-DPC alone on --workload")
+    ap.add_argument("--sapprox-only", action="store_true", help="time S-Approx-DPC alone on --workload")
+    ap.add_argument("--eps", type=float, default=0.5, help="S-Approx-DPC's eps")
     ap.add_argument("--jobs", type=int, default=4096, help="jobs of the batch4096 workload")
     ap.add_argument("--no-autotune", action="store_true", help="batch4096: library defaults for every job")
-    ap.add_argument("--duration", type=float, default=5.0, help="serve: seconds of the Poisson trace")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of the Poisson trace")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent slots (streams)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy kernel of known size, "
@@ -389,6 +432,27 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     job = inputs.WORKLOADS[args.workload]()
+    if args.approx_only:  # Approx-DPC alone (for its kernel traces): no exact run, no comparison
+        r = bench_approx(job, args.steps, args.warmup, None)
+        print(json.dumps({"metric": "points/s end-to-end Approx-DPC (rho+delta+labels) at 1 MI355X",
+                          "value": r["value"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+                          "config": {"workload": job.name, "n": job.n, "d": job.d, "d_cut": job.d_cut},
+                          "kernels_ms_per_step": r["kernels_ms_per_step"],
+                          "approximate_fraction": r["approximate_fraction"]}), flush=True)
+        return 0
+    if args.sapprox_only:  # S-Approx-DPC alone (for its kernel traces)
+        r = bench_sapprox(job, args.steps, args.warmup, args.eps)
+        print(json.dumps({"metric": "points/s end-to-end S-Approx-DPC (rho+delta+labels) at 1 MI355X",
+                          "value": r["value"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+                          "config": {"workload": job.name, "n": job.n, "d": job.d, "d_cut": job.d_cut,
+                                     "eps": args.eps},
+                          "kernels_ms_per_step": r["kernels_ms_per_step"],
+                          "picked_fraction": r["picked_fraction"]}), flush=True)
+        return 0
     res = bench_single(args, job, args.steps, args.warmup, with_roofline=True)
     line = {
         "metric": "points/s end-to-end DPC (rho+delta+labels) at 1 MI355X",
@@ -411,12 +475,22 @@ def main() -> int:
         "work": res["work"],
         "ncenters": res["ncenters"],
     }
+    approx, sapprox = {}, {}
+    if not args.no_approx:
+        approx[job.name] = bench_approx(job, max(3, args.steps // 2), 2, res["label"])
+        sapprox[job.name] = bench_sapprox(job, max(3, args.steps // 2), 2, args.eps)
     if args.extra and args.extra != job.name:
         ex = inputs.WORKLOADS[args.extra]()
         r2 = bench_single(args, ex, max(3, args.steps // 2), 2, with_roofline=True)
         line["extra"] = {ex.name: {"value": r2["value"], "unit": "points/s", "ms_per_step": r2["ms_per_step"],
                                    "kernels_ms_per_step": r2["kernels_ms_per_step"],
                                    "roofline": r2["roofline"]}}
+        if not args.no_approx:
+            approx[ex.name] = bench_approx(ex, max(3, args.steps // 2), 2, r2["label"])
+            sapprox[ex.name] = bench_sapprox(ex, max(3, args.steps // 2), 2, args.eps)
+    if approx:
+        line["approx_dpc"] = approx
+        line["s_approx_dpc"] = sapprox
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(job, args.cpu_budget)
     print(json.dumps(line), flush=True)
@@ -485,7 +559,80 @@ def bench_single(args, job, steps: int, warmup: int, with_roofline: bool) -> dic
     return {"value": job.n * steps / (t1 - t0), "ms_per_step": (t1 - t0) * 1000.0 / steps,
             "kernels_ms_per_step": {k: v[1] / steps for k, v in prof.items() if k != "work" and v[0]},
             "roofline": dict(roofs[dom], kernel=dom), "rooflines": roofs,
-            "work": dict(work, sum_rho=sum_rho), "ncenters": int(out["ncenters"].item())}
+            "work": dict(work, sum_rho=sum_rho), "ncenters": int(out["ncenters"].item()),
+            "label": out["label"]}
+
+
+def bench_sapprox(job, steps: int, warmup: int, eps: float) -> dict:
+    """Time `steps` dpc_sapprox_run calls (S-Approx-DPC, Section 5) on resident input."""
+    import torch
+
+    from paper_2207_04649_amd import dpc
+
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(job.pts).to(dev)
+    ws = torch.empty(dpc.dpc_sapprox_workspace_bytes(job.n, job.d, job.d_cut, eps), dtype=torch.uint8, device=dev)
+    out: dict = {}
+    for _ in range(warmup):
+        dpc.dpc_sapprox_run(pts, job.d_cut, eps, job.rho_min, job.delta_min, ws=ws, out=out)
+    torch.cuda.synchronize()
+    dpc.dpc_sync_status(ws)
+    L = _profile_lib()
+    _report(L)
+    L.dpc_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dpc.dpc_sapprox_run(pts, job.d_cut, eps, job.rho_min, job.delta_min, ws=ws, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.dpc_profile_enable(0)
+    prof = _report(L)
+    dpc.dpc_sync_status(ws)
+    return {"eps": eps, "value": job.n * steps / (t1 - t0), "unit": "points/s",
+            "ms_per_step": (t1 - t0) * 1000.0 / steps,
+            "kernels_ms_per_step": {k: v[1] / steps for k, v in prof.items() if k != "work" and v[0]},
+            "picked_fraction": float(out["picked"].float().mean().item()),
+            "ncenters": int(out["ncenters"].item())}
+
+
+def bench_approx(job, steps: int, warmup: int, exact_label) -> dict:
+    """Time `steps` dpc_approx_run calls (Approx-DPC, Section 4) on resident input, with
+    HIP events per kernel group; report how many points the approximation rules settled
+    and whether the centers equal the exact path's (`exact_label`, a device tensor)."""
+    import torch
+
+    from paper_2207_04649_amd import dpc
+
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(job.pts).to(dev)
+    ws = torch.empty(dpc.dpc_approx_workspace_bytes(job.n, job.d, job.d_cut), dtype=torch.uint8, device=dev)
+    out: dict = {}
+    for _ in range(warmup):
+        dpc.dpc_approx_run(pts, job.d_cut, job.rho_min, job.delta_min, ws=ws, out=out)
+    torch.cuda.synchronize()
+    dpc.dpc_sync_status(ws)
+    L = _profile_lib()
+    _report(L)
+    L.dpc_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dpc.dpc_approx_run(pts, job.d_cut, job.rho_min, job.delta_min, ws=ws, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.dpc_profile_enable(0)
+    prof = _report(L)
+    dpc.dpc_sync_status(ws)
+    same = None
+    if exact_label is not None:
+        ids = torch.arange(job.n, device=dev, dtype=torch.int32)
+        same = bool(torch.equal(out["label"] == ids, exact_label == ids)) and bool(
+            torch.equal(out["label"] < 0, exact_label < 0))
+    return {"value": job.n * steps / (t1 - t0), "unit": "points/s", "ms_per_step": (t1 - t0) * 1000.0 / steps,
+            "kernels_ms_per_step": {k: v[1] / steps for k, v in prof.items() if k != "work" and v[0]},
+            "approximate_fraction": float(out["approx"].float().mean().item()),
+            "centers_and_noise_equal_exact": same}
 
 
 if __name__ == "__main__":
