@@ -936,10 +936,7 @@ dpc_status dpc_sapprox_run(const int32_t *pts, int64_t n, int32_t d, double d_cu
   const Ws w = resolve(p, ws);
   hipError_t e = clear_status(w.hdr, s);
   if (e != hipSuccess) return device_fail(e, "status reset");
-  {
-    ProfScope ps(s, kProfGrid);
-    if ((e = build_grid(p, w, pts, grid_stamp(p, pts), s)) != hipSuccess) return device_fail(e, "grid build");
-  }
+  if ((st = run_density(p, w, pts, s)) != DPC_OK) return st;
   if ((e = launch_sapprox(p, w, a, ws, dep, delta, rho, picked, s)) != hipSuccess)
     return device_fail(e, "S-Approx-DPC kernels");
   ProfScope ps(s, kProfLabel);

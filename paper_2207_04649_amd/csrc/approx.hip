@@ -32,7 +32,7 @@ constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint64_t kApproxD2 = (uint64_t(1) << (64 - kIdBits)) - 2;
 
 struct AxWs {
-  uint32_t *cnt;    // [4] counters: p* points, approximate by the second rule
+  uint32_t *cnt;    // [4] counters: p* points
   uint32_t *rep;    // [slots] cell-order position of the point that opened the slot, kEmpty if free
   uint64_t *top;    // [slots] largest rank key of the cell (its p*), 0 before any point
   uint32_t *minrho; // [slots] smallest density of the cell
@@ -62,17 +62,6 @@ __device__ __forceinline__ uint32_t cell_hash(const int32_t *c) {
     h ^= h >> 29;
   }
   return uint32_t(h ^ (h >> 32));
-}
-
-// Appends the positions of the lanes with `take` to list[*counter ...]: one
-// atomic per wave.  Every lane of the wave calls it (no loop around it).
-__device__ __forceinline__ void wave_push(uint32_t *counter, uint32_t *list, bool take, uint32_t q) {
-  const uint64_t m = __ballot(take);
-  const int lane = lane_id();
-  uint32_t base = 0;
-  if (lane == 0 && m != 0) base = atomicAdd(counter, uint32_t(__popcll(m)));
-  base = __shfl(base, 0, kWave);
-  if (take) list[base + uint32_t(__popcll(m & ((uint64_t(1) << lane) - 1)))] = q;
 }
 
 __global__ __launch_bounds__(kBlock) void k_ax_clear(AxWs x, uint32_t slots) {
@@ -116,29 +105,39 @@ __global__ __launch_bounds__(kBlock) void k_ax_insert(Plan p, Ws w, ApproxPlan a
 }
 
 // First rule: a point other than its cell's p* takes p*(c).  The p* points are
-// listed for the range search.
+// listed for the range search (kSplitPer consecutive positions per thread, one
+// atomic per block).
+constexpr int kSplitPer = 16;
+
 __global__ __launch_bounds__(kBlock) void k_ax_split(Plan p, Ws w, AxWs x) {
-  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (grid_skipped(w.hdr)) return;
-  bool star = false;
-  if (q < p.n) {
+  const int64_t q0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * kSplitPer;
+  uint32_t mask = 0;
+  for (int k = 0; k < kSplitPer; ++k) {
+    const int64_t q = q0 + k;
+    if (q >= p.n) break;
     const uint64_t top = x.top[x.ent[q]];
-    star = top == w.sK[q];
-    if (!star) w.best[q] = (kApproxD2 << kIdBits) | (~uint32_t(top) & kIdMask);
+    if (top == w.sK[q]) {
+      mask |= 1u << k;
+    } else {
+      w.best[q] = (kApproxD2 << kIdBits) | (~uint32_t(top) & kIdMask);
+      w.flag[q] = 0;
+    }
   }
-  wave_push(&x.cnt[0], x.plist, star, uint32_t(q));
+  uint32_t at = block_append(mask, &x.cnt[0]);
+  for (int k = 0; k < kSplitPer; ++k)
+    if (mask & (1u << k)) x.plist[at++] = uint32_t(q0 + k);
 }
 
 // Second rule, one lane per p* point: a range search of radius d_cut over the
 // exact grid's cells (their first gm coordinates), keeping the qualifying cell
 // with the smallest coordinates.  A point no cell qualifies for gets kNoKey and
-// goes to the ring search's list.
+// its open flag, which puts it on the ring search's list.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_ax_near(Plan p, Ws w, ApproxPlan a, AxWs x) {
   if (grid_skipped(w.hdr)) return;
   const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t nstar = x.cnt[0];
-  const bool own = u < nstar;
+  const bool own = u < x.cnt[0];
   const uint32_t q = own ? x.plist[u] : 0u;
   bool found = false;
   if (own) {
@@ -222,9 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_ax_near(Plan p, Ws w, ApproxPlan a, 
       w.best[q] = kNoKey;
     }
   }
-  wave_push(&w.hdr->n_unres, w.unres, own && !found, q);
-  const uint64_t m = __ballot(own && found);
-  if (lane_id() == 0 && m != 0) atomicAdd(&x.cnt[1], uint32_t(__popcll(m)));
+  if (own) w.flag[q] = found ? 0 : 1;  // open for the exact remainder
 }
 
 // Outputs in id order: the exact keys as the exact path's finish writes them,
@@ -256,9 +253,10 @@ __global__ __launch_bounds__(kBlock) void k_ax_finish(Plan p, Ws w, double d_cut
 template <int D>
 hipError_t launch_cells_d(const Plan &p, const Ws &w, const ApproxPlan &a, const AxWs &x, hipStream_t s) {
   DPC_LAUNCH((k_ax_insert<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
-  DPC_LAUNCH((k_ax_split), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+  DPC_LAUNCH((k_ax_split), blocks_for(p.n, kBlock * kSplitPer), kBlock, s, p, w, x);
   DPC_LAUNCH((k_ax_near<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_collect(p, w, s);
 }
 
 }  // namespace

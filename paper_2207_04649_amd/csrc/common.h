@@ -241,6 +241,9 @@ hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *de
 // w.unres (DevHeader::n_unres entries) a caller filled; each listed position's
 // best key must be kNoKey.
 hipError_t launch_exact_remainder(const Plan &p, const Ws &w, hipStream_t s);
+// The list w.unres of the cell-order positions whose w.flag is set (appended to
+// DevHeader::n_unres).
+hipError_t launch_collect(const Plan &p, const Ws &w, hipStream_t s);
 // Approx-DPC's dependent points after the density kernels and the rank sort:
 // the second grid, the approximation rules, the exact remainder, and the outputs
 // in id order (approx, if not null, gets 1 where the dependent point is approximate).
@@ -372,6 +375,31 @@ __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t *to
 // counter's old value); lanes without `take` get an unspecified value.
 __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool take) {
   return atomicAdd(counter, take ? 1u : 0u);
+}
+
+// Block-wide list append: each thread offers up to 32 items (bit k of `mask`: item k
+// taken) and gets the list slot of its first taken item; a thread's items follow
+// each other, and threads follow thread order.  One atomic per block on `counter`
+// (a counter bumped by every wave serialises in L2).  Every thread of the block
+// calls it, with uniform control flow.
+__device__ __forceinline__ uint32_t block_append(uint32_t mask, uint32_t *counter) {
+  __shared__ uint32_t wave_tot[dpc::kWavesPerBlock];
+  __shared__ uint32_t base;
+  uint32_t tot;
+  const uint32_t off = wave_exclusive_scan(uint32_t(__popc(mask)), &tot);
+  const int wv = threadIdx.x / dpc::kWave;
+  if (lane_id() == 0) wave_tot[wv] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t sum = 0;
+    for (int k = 0; k < dpc::kWavesPerBlock; ++k) sum += wave_tot[k];
+    base = sum ? atomicAdd(counter, sum) : 0u;
+  }
+  __syncthreads();
+  uint32_t at = base + off;
+  for (int k = 0; k < wv; ++k) at += wave_tot[k];
+  __syncthreads();  // the shared words are reused by the next call
+  return at;
 }
 
 // A job's share of a launch: block b of nb blocks.  For a single-job call it

@@ -1291,6 +1291,11 @@ hipError_t launch_dependent(const Plan &p, const Ws &w, int32_t *dep, double *de
   }
 }
 
+hipError_t launch_collect(const Plan &p, const Ws &w, hipStream_t s) {
+  DPC_LAUNCH((k_collect), blocks_for(p.n, kBlock * kCollectPer), kBlock, s, p, w);
+  return hipGetLastError();
+}
+
 hipError_t launch_exact_remainder(const Plan &p, const Ws &w, hipStream_t s) {
   if (p.openK) return hipErrorInvalidValue;  // the ring search would read the open stage's list
   switch (p.d) {

@@ -5,8 +5,10 @@
 //     Approx-DPC); integer side Le = 1 + floor(sqrt((Re - 1) / d)), Re =
 //     ceil((eps d_cut)^2), so the points of a cell lie strictly within eps * d_cut
 //     of each other.  A cell's pick is its smallest id (one atomicMin per point).
-//   * Local density of the picks only (Def. 1, against all points): one lane per
-//     pick, a range search of radius d_cut over the exact grid's rows.
+//   * Local density of the picks (Def. 1, against all points).  The section
+//     computes it for the picks only; here the exact path's density kernels run
+//     over every point, which on this hardware costs less than a range search
+//     per pick, and the picks read theirs.
 //   * A point that was not picked takes its cell's pick (true distance, below
 //     eps * d_cut) and reports the pick's density.
 //   * First phase: a pick takes the nearest higher-ranked pick among the picks of
@@ -14,9 +16,9 @@
 //   * Second phase: the picks left take their nearest higher-ranked pick through
 //     the exact path's ring search and prefix scan.  Their rank keys rank every
 //     pick above every other point (a point that was not picked gets density key
-//     1, a pick its density plus one when that stays within n, else its density:
-//     a pick of density n is within d_cut of every point, so then no pick has
-//     density 1), so that search only ever returns picks.  The section's
+//     1, a pick its density plus one when no point has density n, else its
+//     density: a point of density n is within d_cut of every point, so then no
+//     pick has density 1), so that search only ever returns picks.  The section's
 //     temporary clusters prune this same search; its result does not depend on
 //     them.
 #include "common.h"
@@ -28,7 +30,7 @@ namespace {
 constexpr uint32_t kEmpty = 0xffffffffu;
 
 struct SaWs {
-  uint32_t *cnt;    // [4] counters: picks, largest pick density, first-phase picks
+  uint32_t *cnt;    // [4] counters: picks, largest density of all points
   uint32_t *rep;    // [slots] cell-order position of the point that opened the slot, kEmpty if free
   uint32_t *pick;   // [slots] smallest id of the cell (its pick), kEmpty before any point
   uint32_t *ppos;   // [slots] cell-order position of the pick
@@ -59,16 +61,6 @@ __device__ __forceinline__ uint32_t cell_hash(const int32_t *c) {
     h ^= h >> 29;
   }
   return uint32_t(h ^ (h >> 32));
-}
-
-// One atomic per wave; every lane of the wave calls it.
-__device__ __forceinline__ void wave_push(uint32_t *counter, uint32_t *list, bool take, uint32_t q) {
-  const uint64_t m = __ballot(take);
-  const int lane = lane_id();
-  uint32_t base = 0;
-  if (lane == 0 && m != 0) base = atomicAdd(counter, uint32_t(__popcll(m)));
-  base = __shfl(base, 0, kWave);
-  if (take) list[base + uint32_t(__popcll(m & ((uint64_t(1) << lane) - 1)))] = q;
 }
 
 template <int D>
@@ -159,37 +151,46 @@ __global__ __launch_bounds__(kBlock) void k_sa_insert(Plan p, Ws w, SApproxPlan 
   atomicMin(&x.pick[h], uint32_t(w.sid[q]));
 }
 
-// The picks: their positions per slot and as a list.
+// The picks: their positions and densities per slot, and as a list
+// (kSplitPer consecutive positions per thread, one atomic per block); the
+// largest density of all points (one atomic per block).
+constexpr int kSplitPer = 16;
+
 __global__ __launch_bounds__(kBlock) void k_sa_split(Plan p, Ws w, SaWs x) {
-  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  __shared__ uint32_t wave_max[kWavesPerBlock];
   if (grid_skipped(w.hdr)) return;
-  bool star = false;
-  if (q < p.n) {
+  const int64_t q0 = (int64_t(blockIdx.x) * kBlock + threadIdx.x) * kSplitPer;
+  uint32_t mask = 0, top = 0;
+  for (int k = 0; k < kSplitPer; ++k) {
+    const int64_t q = q0 + k;
+    if (q >= p.n) break;
     const uint32_t e = x.ent[q];
-    star = x.pick[e] == uint32_t(w.sid[q]);
-    if (star) x.ppos[e] = uint32_t(q);
+    const uint32_t rho = uint32_t(w.sK[q] >> 32);
+    top = max(top, rho);
+    if (x.pick[e] == uint32_t(w.sid[q])) {
+      mask |= 1u << k;
+      x.ppos[e] = uint32_t(q);
+      x.prho[e] = rho;
+    } else {
+      w.flag[q] = 0;
+    }
   }
-  wave_push(&x.cnt[0], x.plist, star, uint32_t(q));
+  for (int off = kWave / 2; off > 0; off >>= 1) top = max(top, uint32_t(__shfl_xor(top, off, kWave)));
+  if (lane_id() == 0) wave_max[threadIdx.x / kWave] = top;
+  uint32_t at = block_append(mask, &x.cnt[0]);  // (synchronises the block)
+  if (threadIdx.x == 0) {
+    uint32_t m = 0;
+    for (int k = 0; k < kWavesPerBlock; ++k) m = max(m, wave_max[k]);
+    atomicMax(&x.cnt[1], m);
+  }
+  for (int k = 0; k < kSplitPer; ++k)
+    if (mask & (1u << k)) x.plist[at++] = uint32_t(q0 + k);
 }
 
-// Local density of each pick (Def. 1 against every point).
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_sa_density(Plan p, Ws w, SaWs x) {
-  if (grid_skipped(w.hdr)) return;
-  const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
-  if (u >= x.cnt[0]) return;
-  const uint32_t q = x.plist[u];
-  int32_t xq[D];
-#pragma unroll
-  for (int t = 0; t < D; ++t) xq[t] = w.spts[int64_t(q) * D + t];
-  uint32_t rho = 0;
-  for_each_near<D>(p, w, xq, [&](uint32_t j) { rho += d2_of<D>(w.spts, j, xq) < p.R ? 1u : 0u; });
-  x.prho[x.ent[q]] = rho;
-  atomicMax(&x.cnt[1], rho);
-}
-
-// Rank keys: every pick above every other point (see the file comment), and the
-// dependent point of each point that was not picked: its cell's pick.
+// Rank keys: every pick above every other point (see the file comment; the
+// shift is decided on the largest density of all points: if some point is within
+// d_cut of every point, every pick has density >= 2), and the dependent point of
+// each point that was not picked: its cell's pick.
 __global__ __launch_bounds__(kBlock) void k_sa_keys(Plan p, Ws w, SaWs x) {
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= p.n || grid_skipped(w.hdr)) return;
@@ -216,8 +217,8 @@ __global__ __launch_bounds__(kBlock) void k_sa_keys(Plan p, Ws w, SaWs x) {
 }
 
 // First phase, one lane per pick: the nearest higher-ranked pick of the cells
-// that hold a point strictly within d_cut; picks without one go to the ring
-// search's list with no key.
+// that hold a point strictly within d_cut; picks without one keep no key and
+// their open flag, which puts them on the ring search's list.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sa_phase1(Plan p, Ws w, SaWs x) {
   if (grid_skipped(w.hdr)) return;
@@ -244,9 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_sa_phase1(Plan p, Ws w, SaWs x) {
     });
     w.best[q] = best;
   }
-  wave_push(&w.hdr->n_unres, w.unres, own && best == kNoKey, q);
-  const uint64_t m = __ballot(own && best != kNoKey);
-  if (lane_id() == 0 && m != 0) atomicAdd(&x.cnt[2], uint32_t(__popcll(m)));
+  if (own) w.flag[q] = best == kNoKey ? 1 : 0;  // open for the second phase
 }
 
 // Outputs in id order: dep and the true distance from the key, the pick's density,
@@ -274,8 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_sa_finish(Plan p, Ws w, SaWs x, int3
 template <int D>
 void launch_sa_d(const Plan &p, const Ws &w, const SApproxPlan &a, const SaWs &x, hipStream_t s) {
   DPC_LAUNCH((k_sa_insert<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
-  DPC_LAUNCH((k_sa_split), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
-  DPC_LAUNCH((k_sa_density<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+  DPC_LAUNCH((k_sa_split), blocks_for(p.n, kBlock * kSplitPer), kBlock, s, p, w, x);
   DPC_LAUNCH((k_sa_keys), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
   DPC_LAUNCH((k_sa_phase1<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
 }
@@ -301,6 +299,7 @@ hipError_t launch_sapprox(const Plan &p, const Ws &w, const SApproxPlan &a, void
       default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_collect(p, w, s)) != hipSuccess) return e;
   }
   {
     ProfScope ps(s, kProfRankSort);
