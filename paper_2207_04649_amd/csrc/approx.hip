@@ -20,6 +20,7 @@
 // one kd-tree each, Section 4.3) is replaced by that search: both return the
 // exact dependent point.
 #include "common.h"
+#include "near.h"
 #include "prof.h"
 
 namespace dpc {
@@ -129,99 +130,82 @@ __global__ __launch_bounds__(kBlock) void k_ax_split(Plan p, Ws w, AxWs x) {
     if (mask & (1u << k)) x.plist[at++] = uint32_t(q0 + k);
 }
 
-// Second rule, one lane per p* point: a range search of radius d_cut over the
-// exact grid's cells (their first gm coordinates), keeping the qualifying cell
-// with the smallest coordinates.  A point no cell qualifies for gets kNoKey and
-// its open flag, which puts it on the ring search's list.
+// Second rule, one wave per p* point: a range search of radius d_cut over the
+// exact grid's rows, keeping the qualifying cell with the smallest coordinates
+// (each lane its own, then a reduction over the wave).  A point no cell
+// qualifies for gets kNoKey and its open flag, which puts it on the ring search's
+// list.
+template <int D>
+__device__ __forceinline__ bool lex_less(const int32_t *a, const int32_t *b) {
+  bool less = false, eq = true;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    less = less || (eq && a[t] < b[t]);
+    eq = eq && a[t] == b[t];
+  }
+  return less;
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_ax_near(Plan p, Ws w, ApproxPlan a, AxWs x) {
+  __shared__ NearLds lds_all[kWavesPerBlock];
+  NearLds &lds = lds_all[threadIdx.x / kWave];
   if (grid_skipped(w.hdr)) return;
-  const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
-  const bool own = u < x.cnt[0];
-  const uint32_t q = own ? x.plist[u] : 0u;
-  bool found = false;
-  if (own) {
+  const Blk blk = grid_blk();
+  const uint32_t nstar = uniform(x.cnt[0]);
+  const uint32_t nw = grid_waves(blk);
+  for (uint32_t u = wave_index(blk); u < nstar; u += nw) {
+    const uint32_t q = uniform(x.plist[u]);
     int32_t xq[D];
 #pragma unroll
-    for (int t = 0; t < D; ++t) xq[t] = w.spts[int64_t(q) * D + t];
-    const uint32_t e = x.ent[q];
-    const uint32_t rho = uint32_t(w.sK[q] >> 32);
-    const int32_t L = p.L, nc = p.nc, gm = p.gm, r0 = p.L0;
-    const int last = gm - 1;
-    int32_t lo[D], hi[D], cur[D], bc[D];  // bc: best qualifying cell so far
-    int32_t lo_l = 0, hi_l = 0;           // cell range along the last grid dimension
+    for (int t = 0; t < D; ++t) xq[t] = uniform(w.spts[int64_t(q) * D + t]);
+    const uint32_t e = uniform(x.ent[q]);
+    const uint32_t rho = uniform(uint32_t(w.sK[q] >> 32));
+    int32_t bc[D];  // this lane's best qualifying cell
 #pragma unroll
-    for (int t = 0; t < D; ++t) {
-      lo[t] = t < gm ? max(xq[t] - r0, 0) / L : 0;
-      hi[t] = t < gm ? min(xq[t] + r0, DPC_COORD_LIMIT - 1) / L : 0;
-      cur[t] = lo[t];
-      bc[t] = 0;
-      if (t == last) {
-        lo_l = lo[t];
-        hi_l = hi[t];
-      }
-    }
+    for (int t = 0; t < D; ++t) bc[t] = 0;
     uint32_t be = 0;
-    for (;;) {
-      // one row: cells lo_l .. hi_l along the last grid dimension are
-      // consecutive in the table, so their points are one run of positions
-      int64_t row = 0;
+    int found = 0;
+    wave_near<D>(p, w, xq, lds, [&](uint32_t j) {
+      // a point of a qualifying cell has a higher density: test that first
+      if (uint32_t(w.sK[j] >> 32) <= rho) return;
+      int64_t d2 = 0;
 #pragma unroll
-      for (int t = 0; t < D; ++t)
-        if (t < last) row = row * nc + cur[t];
-      const int64_t c0 = row * nc + lo_l;
-      const uint32_t j0 = w.cnt[c0], j1 = w.cnt[c0 + (hi_l - lo_l) + 1];
-      for (uint32_t j = j0; j < j1; ++j) {
-        // a point of a qualifying cell has a higher density: test that first
-        if (uint32_t(w.sK[j] >> 32) <= rho) continue;
-        int64_t d2 = 0;
-#pragma unroll
-        for (int t = 0; t < D; ++t) {
-          const int64_t df = int64_t(w.spts[int64_t(j) * D + t]) - xq[t];
-          d2 += df * df;
-        }
-        if (d2 >= p.R) continue;
-        const uint32_t e2 = x.ent[j];
-        if (e2 == e || x.minrho[e2] <= rho) continue;
-        int32_t cc[D];
-#pragma unroll
-        for (int t = 0; t < D; ++t) cc[t] = w.spts[int64_t(j) * D + t] / a.La;
-        bool less = !found;
-        bool eq = true;
-#pragma unroll
-        for (int t = 0; t < D; ++t) {
-          less = less || (eq && cc[t] < bc[t]);
-          eq = eq && cc[t] == bc[t];
-        }
-        if (less) {
-#pragma unroll
-          for (int t = 0; t < D; ++t) bc[t] = cc[t];
-          be = e2;
-          found = true;
-        }
+      for (int t = 0; t < D; ++t) {
+        const int64_t df = int64_t(w.spts[int64_t(j) * D + t]) - xq[t];
+        d2 += df * df;
       }
-      // next row: an odometer over the grid dimensions before the last
-      bool carry = true;
+      if (d2 >= p.R) return;
+      const uint32_t e2 = x.ent[j];
+      if (e2 == e || x.minrho[e2] <= rho) return;
+      int32_t cc[D];
 #pragma unroll
-      for (int t = D - 1; t >= 0; --t) {
-        if (t < last && carry) {
-          if (cur[t] < hi[t]) {
-            ++cur[t];
-            carry = false;
-          } else {
-            cur[t] = lo[t];
-          }
-        }
+      for (int t = 0; t < D; ++t) cc[t] = w.spts[int64_t(j) * D + t] / a.La;
+      if (!found || lex_less<D>(cc, bc)) {
+#pragma unroll
+        for (int t = 0; t < D; ++t) bc[t] = cc[t];
+        be = e2;
+        found = 1;
       }
-      if (carry) break;
+    });
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      int32_t oc[D];
+#pragma unroll
+      for (int t = 0; t < D; ++t) oc[t] = __shfl_xor(bc[t], off, kWave);
+      const uint32_t oe = __shfl_xor(be, off, kWave);
+      const int of = __shfl_xor(found, off, kWave);
+      if (of && (!found || lex_less<D>(oc, bc))) {
+#pragma unroll
+        for (int t = 0; t < D; ++t) bc[t] = oc[t];
+        be = oe;
+        found = 1;
+      }
     }
-    if (found) {
-      w.best[q] = (kApproxD2 << kIdBits) | (~uint32_t(x.top[be]) & kIdMask);
-    } else {
-      w.best[q] = kNoKey;
+    if (lane_id() == 0) {  // every lane holds the same winner
+      w.best[q] = found ? (kApproxD2 << kIdBits) | (~uint32_t(x.top[be]) & kIdMask) : kNoKey;
+      w.flag[q] = found ? 0 : 1;  // open for the exact remainder
     }
   }
-  if (own) w.flag[q] = found ? 0 : 1;  // open for the exact remainder
 }
 
 // Outputs in id order: the exact keys as the exact path's finish writes them,
@@ -254,7 +238,7 @@ template <int D>
 hipError_t launch_cells_d(const Plan &p, const Ws &w, const ApproxPlan &a, const AxWs &x, hipStream_t s) {
   DPC_LAUNCH((k_ax_insert<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
   DPC_LAUNCH((k_ax_split), blocks_for(p.n, kBlock * kSplitPer), kBlock, s, p, w, x);
-  DPC_LAUNCH((k_ax_near<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
+  DPC_LAUNCH((k_ax_near<D>), persistent_blocks(p.n), kBlock, s, p, w, a, x);
   hipError_t e = hipGetLastError();
   return e != hipSuccess ? e : launch_collect(p, w, s);
 }

@@ -1,0 +1,86 @@
+// Wave-cooperative range scan over the exact grid, for the approximate methods'
+// per-point searches of radius d_cut.
+#pragma once
+
+#include "common.h"
+
+namespace dpc {
+
+// Per-wave LDS of wave_near: one group of up to 64 rows at a time.
+struct NearLds {
+  uint32_t off[kWave];  // exclusive prefix of the rows' point counts
+  uint32_t j0[kWave];   // first cell-order position of each row
+};
+
+// Calls f(j) once, on some lane of the calling wave, for every cell-order position
+// j of the exact grid's rows that can hold a point within d_cut of xq (the same for
+// every lane): the box of radius floor(sqrt(R - 1)) over the first gm coordinates,
+// whose cells along the last grid dimension form one run of positions per row.
+// The rows are taken 64 at a time, one per lane; their runs are flattened by a
+// prefix sum so that consecutive lanes read consecutive positions.
+template <int D, class F>
+__device__ __forceinline__ void wave_near(const Plan &p, const Ws &w, const int32_t *xq, NearLds &lds, F &&f) {
+  const int lane = lane_id();
+  const int32_t L = p.L, nc = p.nc, gm = p.gm, r0 = p.L0;
+  const int last = gm - 1;
+  int32_t lo[D], ext[D];
+  int32_t lo_l = 0, ext_l = 1;
+  uint32_t nrows = 1;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    lo[t] = 0;
+    ext[t] = 1;
+    if (t < gm) {
+      const int32_t a = max(xq[t] - r0, 0) / L, b = min(xq[t] + r0, DPC_COORD_LIMIT - 1) / L;
+      if (t == last) {
+        lo_l = a;
+        ext_l = b - a + 1;
+      } else {
+        lo[t] = a;
+        ext[t] = b - a + 1;
+        nrows *= uint32_t(ext[t]);
+      }
+    }
+  }
+  for (uint32_t g = 0; g < nrows; g += kWave) {
+    const uint32_t r = g + uint32_t(lane);
+    uint32_t len = 0, j0 = 0;
+    if (r < nrows) {
+      // row r in row-major order of the dimensions before the last
+      uint32_t rem = r;
+      int64_t row = 0, scale = 1;
+#pragma unroll
+      for (int t = D - 1; t >= 0; --t) {
+        if (t < last) {
+          const uint32_t dig = rem % uint32_t(ext[t]);
+          rem /= uint32_t(ext[t]);
+          row += int64_t(lo[t] + int32_t(dig)) * scale;
+          scale *= nc;
+        }
+      }
+      const int64_t c0 = row * nc + lo_l;
+      j0 = w.cnt[c0];
+      len = w.cnt[c0 + ext_l] - j0;
+    }
+    uint32_t total;
+    const uint32_t off = wave_exclusive_scan(len, &total);
+    lds.off[lane] = off;
+    lds.j0[lane] = j0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (uint32_t k = uint32_t(lane); k < total; k += kWave) {
+      // the row holding flattened index k: the last with off <= k
+      uint32_t a = 0, b = kWave - 1;
+      while (a < b) {
+        const uint32_t m = (a + b + 1) >> 1;
+        if (lds.off[m] <= k) a = m;
+        else b = m - 1;
+      }
+      f(lds.j0[a] + (k - lds.off[a]));
+    }
+    __builtin_amdgcn_wave_barrier();  // every lane has read the group before it is overwritten
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+}
+
+}  // namespace dpc

@@ -22,6 +22,7 @@
 //     temporary clusters prune this same search; its result does not depend on
 //     them.
 #include "common.h"
+#include "near.h"
 #include "prof.h"
 
 namespace dpc {
@@ -72,49 +73,6 @@ __device__ __forceinline__ int64_t d2_of(const int32_t *__restrict__ spts, uint3
     s += df * df;
   }
   return s;
-}
-
-// Visits every cell-order position j of the exact grid's rows that can hold a
-// point within d_cut of xq (the box of radius floor(sqrt(R - 1)) over the first gm
-// coordinates; its cells along the last grid dimension are one run of positions).
-template <int D, class F>
-__device__ __forceinline__ void for_each_near(const Plan &p, const Ws &w, const int32_t *xq, F &&f) {
-  const int32_t L = p.L, nc = p.nc, gm = p.gm, r0 = p.L0;
-  const int last = gm - 1;
-  int32_t lo[D], hi[D], cur[D];
-  int32_t lo_l = 0, hi_l = 0;
-#pragma unroll
-  for (int t = 0; t < D; ++t) {
-    lo[t] = t < gm ? max(xq[t] - r0, 0) / L : 0;
-    hi[t] = t < gm ? min(xq[t] + r0, DPC_COORD_LIMIT - 1) / L : 0;
-    cur[t] = lo[t];
-    if (t == last) {
-      lo_l = lo[t];
-      hi_l = hi[t];
-    }
-  }
-  for (;;) {
-    int64_t row = 0;
-#pragma unroll
-    for (int t = 0; t < D; ++t)
-      if (t < last) row = row * nc + cur[t];
-    const int64_t c0 = row * nc + lo_l;
-    const uint32_t j0 = w.cnt[c0], j1 = w.cnt[c0 + (hi_l - lo_l) + 1];
-    for (uint32_t j = j0; j < j1; ++j) f(j);
-    bool carry = true;
-#pragma unroll
-    for (int t = D - 1; t >= 0; --t) {
-      if (t < last && carry) {
-        if (cur[t] < hi[t]) {
-          ++cur[t];
-          carry = false;
-        } else {
-          cur[t] = lo[t];
-        }
-      }
-    }
-    if (carry) break;
-  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sa_clear(SaWs x, uint32_t slots) {
@@ -216,24 +174,28 @@ __global__ __launch_bounds__(kBlock) void k_sa_keys(Plan p, Ws w, SaWs x) {
   }
 }
 
-// First phase, one lane per pick: the nearest higher-ranked pick of the cells
-// that hold a point strictly within d_cut; picks without one keep no key and
-// their open flag, which puts them on the ring search's list.
+// First phase, one wave per pick: the nearest higher-ranked pick of the cells
+// that hold a point strictly within d_cut (each lane its own, then the wave's
+// minimum); picks without one keep no key and their open flag, which puts them on
+// the ring search's list.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sa_phase1(Plan p, Ws w, SaWs x) {
+  __shared__ NearLds lds_all[kWavesPerBlock];
+  NearLds &lds = lds_all[threadIdx.x / kWave];
   if (grid_skipped(w.hdr)) return;
-  const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
-  const bool own = u < x.cnt[0];
-  const uint32_t q = own ? x.plist[u] : 0u;
-  uint64_t best = kNoKey;
-  if (own) {
+  const Blk blk = grid_blk();
+  const uint32_t npick = uniform(x.cnt[0]);
+  const uint32_t nw = grid_waves(blk);
+  for (uint32_t u = wave_index(blk); u < npick; u += nw) {
+    const uint32_t q = uniform(x.plist[u]);
     int32_t xq[D];
 #pragma unroll
-    for (int t = 0; t < D; ++t) xq[t] = w.spts[int64_t(q) * D + t];
-    const uint32_t e = x.ent[q];
-    const uint32_t rho = x.prho[e], id = uint32_t(w.sid[q]);
+    for (int t = 0; t < D; ++t) xq[t] = uniform(w.spts[int64_t(q) * D + t]);
+    const uint32_t e = uniform(x.ent[q]);
+    const uint32_t rho = uniform(x.prho[e]), id = uniform(uint32_t(w.sid[q]));
+    uint64_t best = kNoKey;
     uint32_t last_e = e;  // consecutive positions often share a cell
-    for_each_near<D>(p, w, xq, [&](uint32_t j) {
+    wave_near<D>(p, w, xq, lds, [&](uint32_t j) {
       const uint32_t e2 = x.ent[j];
       if (e2 == e || e2 == last_e) return;
       if (d2_of<D>(w.spts, j, xq) >= p.R) return;
@@ -243,9 +205,12 @@ __global__ __launch_bounds__(kBlock) void k_sa_phase1(Plan p, Ws w, SaWs x) {
       const uint64_t key = (uint64_t(d2_of<D>(w.spts, x.ppos[e2], xq)) << kIdBits) | id2;
       best = key < best ? key : best;
     });
-    w.best[q] = best;
+    best = wave_min_u64(best);
+    if (lane_id() == 0) {
+      w.best[q] = best;
+      w.flag[q] = best == kNoKey ? 1 : 0;  // open for the second phase
+    }
   }
-  if (own) w.flag[q] = best == kNoKey ? 1 : 0;  // open for the second phase
 }
 
 // Outputs in id order: dep and the true distance from the key, the pick's density,
@@ -275,7 +240,7 @@ void launch_sa_d(const Plan &p, const Ws &w, const SApproxPlan &a, const SaWs &x
   DPC_LAUNCH((k_sa_insert<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
   DPC_LAUNCH((k_sa_split), blocks_for(p.n, kBlock * kSplitPer), kBlock, s, p, w, x);
   DPC_LAUNCH((k_sa_keys), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
-  DPC_LAUNCH((k_sa_phase1<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+  DPC_LAUNCH((k_sa_phase1<D>), persistent_blocks(p.n), kBlock, s, p, w, x);
 }
 
 }  // namespace
