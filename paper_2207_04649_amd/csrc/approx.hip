@@ -130,11 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_ax_split(Plan p, Ws w, AxWs x) {
     if (mask & (1u << k)) x.plist[at++] = uint32_t(q0 + k);
 }
 
-// Second rule, one wave per p* point: a range search of radius d_cut over the
-// exact grid's rows, keeping the qualifying cell with the smallest coordinates
-// (each lane its own, then a reduction over the wave).  A point no cell
-// qualifies for gets kNoKey and its open flag, which puts it on the ring search's
-// list.
+// Second rule: a range search of radius d_cut around each p* point over the
+// exact grid's rows, keeping the qualifying cell with the smallest coordinates.
+// A point no cell qualifies for gets kNoKey and its open flag, which puts it on
+// the ring search's list.
 template <int D>
 __device__ __forceinline__ bool lex_less(const int32_t *a, const int32_t *b) {
   bool less = false, eq = true;
@@ -146,6 +145,40 @@ __device__ __forceinline__ bool lex_less(const int32_t *a, const int32_t *b) {
   return less;
 }
 
+// One candidate j of p*'s range search: a point strictly within d_cut, of higher
+// density, in another cell whose points all have a higher density, updates the
+// best qualifying cell (bc, be) when its cell's coordinates are smaller.
+template <int D>
+__device__ __forceinline__ void ax_visit(const Plan &p, const Ws &w, const ApproxPlan &a, const AxWs &x,
+                                         const int32_t *xq, uint32_t e, uint32_t rho, uint32_t j, int &found,
+                                         int32_t *bc, uint32_t &be) {
+  if (uint32_t(w.sK[j] >> 32) <= rho) return;  // cheapest test first
+  int64_t d2 = 0;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    const int64_t df = int64_t(w.spts[int64_t(j) * D + t]) - xq[t];
+    d2 += df * df;
+  }
+  if (d2 >= p.R) return;
+  const uint32_t e2 = x.ent[j];
+  if (e2 == e || x.minrho[e2] <= rho) return;
+  int32_t cc[D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) cc[t] = w.spts[int64_t(j) * D + t] / a.La;
+  if (!found || lex_less<D>(cc, bc)) {
+#pragma unroll
+    for (int t = 0; t < D; ++t) bc[t] = cc[t];
+    be = e2;
+    found = 1;
+  }
+}
+
+__device__ __forceinline__ uint64_t ax_key(const AxWs &x, int found, uint32_t be) {
+  return found ? (kApproxD2 << kIdBits) | (~uint32_t(x.top[be]) & kIdMask) : kNoKey;
+}
+
+// Dense data (task-form plans): one wave per p* point, each lane keeping its own
+// best cell, then a reduction over the wave.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_ax_near(Plan p, Ws w, ApproxPlan a, AxWs x) {
   __shared__ NearLds lds_all[kWavesPerBlock];
@@ -161,33 +194,12 @@ __global__ __launch_bounds__(kBlock) void k_ax_near(Plan p, Ws w, ApproxPlan a, 
     for (int t = 0; t < D; ++t) xq[t] = uniform(w.spts[int64_t(q) * D + t]);
     const uint32_t e = uniform(x.ent[q]);
     const uint32_t rho = uniform(uint32_t(w.sK[q] >> 32));
-    int32_t bc[D];  // this lane's best qualifying cell
+    int32_t bc[D];
 #pragma unroll
     for (int t = 0; t < D; ++t) bc[t] = 0;
     uint32_t be = 0;
     int found = 0;
-    wave_near<D>(p, w, xq, lds, [&](uint32_t j) {
-      // a point of a qualifying cell has a higher density: test that first
-      if (uint32_t(w.sK[j] >> 32) <= rho) return;
-      int64_t d2 = 0;
-#pragma unroll
-      for (int t = 0; t < D; ++t) {
-        const int64_t df = int64_t(w.spts[int64_t(j) * D + t]) - xq[t];
-        d2 += df * df;
-      }
-      if (d2 >= p.R) return;
-      const uint32_t e2 = x.ent[j];
-      if (e2 == e || x.minrho[e2] <= rho) return;
-      int32_t cc[D];
-#pragma unroll
-      for (int t = 0; t < D; ++t) cc[t] = w.spts[int64_t(j) * D + t] / a.La;
-      if (!found || lex_less<D>(cc, bc)) {
-#pragma unroll
-        for (int t = 0; t < D; ++t) bc[t] = cc[t];
-        be = e2;
-        found = 1;
-      }
-    });
+    wave_near<D>(p, w, xq, lds, [&](uint32_t j) { ax_visit<D>(p, w, a, x, xq, e, rho, j, found, bc, be); });
     for (int off = kWave / 2; off > 0; off >>= 1) {
       int32_t oc[D];
 #pragma unroll
@@ -202,10 +214,32 @@ __global__ __launch_bounds__(kBlock) void k_ax_near(Plan p, Ws w, ApproxPlan a, 
       }
     }
     if (lane_id() == 0) {  // every lane holds the same winner
-      w.best[q] = found ? (kApproxD2 << kIdBits) | (~uint32_t(x.top[be]) & kIdMask) : kNoKey;
+      w.best[q] = ax_key(x, found, be);
       w.flag[q] = found ? 0 : 1;  // open for the exact remainder
     }
   }
+}
+
+// Sparse data (lane-form plans): one lane per p* point.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ax_near_lanes(Plan p, Ws w, ApproxPlan a, AxWs x) {
+  if (grid_skipped(w.hdr)) return;
+  const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
+  if (u >= x.cnt[0]) return;
+  const uint32_t q = x.plist[u];
+  int32_t xq[D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) xq[t] = w.spts[int64_t(q) * D + t];
+  const uint32_t e = x.ent[q];
+  const uint32_t rho = uint32_t(w.sK[q] >> 32);
+  int32_t bc[D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) bc[t] = 0;
+  uint32_t be = 0;
+  int found = 0;
+  lane_near<D>(p, w, xq, [&](uint32_t j) { ax_visit<D>(p, w, a, x, xq, e, rho, j, found, bc, be); });
+  w.best[q] = ax_key(x, found, be);
+  w.flag[q] = found ? 0 : 1;  // open for the exact remainder
 }
 
 // Outputs in id order: the exact keys as the exact path's finish writes them,
@@ -238,7 +272,10 @@ template <int D>
 hipError_t launch_cells_d(const Plan &p, const Ws &w, const ApproxPlan &a, const AxWs &x, hipStream_t s) {
   DPC_LAUNCH((k_ax_insert<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
   DPC_LAUNCH((k_ax_split), blocks_for(p.n, kBlock * kSplitPer), kBlock, s, p, w, x);
-  DPC_LAUNCH((k_ax_near<D>), persistent_blocks(p.n), kBlock, s, p, w, a, x);
+  if (p.lanes)
+    DPC_LAUNCH((k_ax_near_lanes<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
+  else
+    DPC_LAUNCH((k_ax_near<D>), persistent_blocks(p.n), kBlock, s, p, w, a, x);
   hipError_t e = hipGetLastError();
   return e != hipSuccess ? e : launch_collect(p, w, s);
 }

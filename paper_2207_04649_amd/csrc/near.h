@@ -6,6 +6,50 @@
 
 namespace dpc {
 
+// Calls f(j) on the calling lane for every cell-order position j of the exact
+// grid's rows that can hold a point within d_cut of xq (the lane's own query):
+// the same box as wave_near, row by row with an odometer.  For sparse data, where
+// a query has few candidates and a wave's setup would cost more than its scan.
+template <int D, class F>
+__device__ __forceinline__ void lane_near(const Plan &p, const Ws &w, const int32_t *xq, F &&f) {
+  const int32_t L = p.L, nc = p.nc, gm = p.gm, r0 = p.L0;
+  const int last = gm - 1;
+  int32_t lo[D], hi[D], cur[D];
+  int32_t lo_l = 0, hi_l = 0;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    lo[t] = t < gm ? max(xq[t] - r0, 0) / L : 0;
+    hi[t] = t < gm ? min(xq[t] + r0, DPC_COORD_LIMIT - 1) / L : 0;
+    cur[t] = lo[t];
+    if (t == last) {
+      lo_l = lo[t];
+      hi_l = hi[t];
+    }
+  }
+  for (;;) {
+    int64_t row = 0;
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+      if (t < last) row = row * nc + cur[t];
+    const int64_t c0 = row * nc + lo_l;
+    const uint32_t j0 = w.cnt[c0], j1 = w.cnt[c0 + (hi_l - lo_l) + 1];
+    for (uint32_t j = j0; j < j1; ++j) f(j);
+    bool carry = true;  // next row: an odometer over the dimensions before the last
+#pragma unroll
+    for (int t = D - 1; t >= 0; --t) {
+      if (t < last && carry) {
+        if (cur[t] < hi[t]) {
+          ++cur[t];
+          carry = false;
+        } else {
+          cur[t] = lo[t];
+        }
+      }
+    }
+    if (carry) break;
+  }
+}
+
 // Per-wave LDS of wave_near: one group of up to 64 rows at a time.
 struct NearLds {
   uint32_t off[kWave];  // exclusive prefix of the rows' point counts

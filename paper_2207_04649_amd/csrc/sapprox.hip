@@ -174,10 +174,24 @@ __global__ __launch_bounds__(kBlock) void k_sa_keys(Plan p, Ws w, SaWs x) {
   }
 }
 
-// First phase, one wave per pick: the nearest higher-ranked pick of the cells
-// that hold a point strictly within d_cut (each lane its own, then the wave's
-// minimum); picks without one keep no key and their open flag, which puts them on
-// the ring search's list.
+// First phase: the nearest higher-ranked pick of the cells that hold a point
+// strictly within d_cut; picks without one keep no key and their open flag, which
+// puts them on the ring search's list.  One candidate j:
+template <int D>
+__device__ __forceinline__ void sa_visit_d(const Plan &p, const Ws &w, const SaWs &x, const int32_t *xq,
+                                           uint32_t e, uint32_t rho, uint32_t id, uint32_t j, uint32_t &last_e,
+                                           uint64_t &best) {
+  const uint32_t e2 = x.ent[j];
+  if (e2 == e || e2 == last_e) return;  // consecutive positions often share a cell
+  if (d2_of<D>(w.spts, j, xq) >= p.R) return;
+  last_e = e2;
+  const uint32_t r2 = x.prho[e2], id2 = x.pick[e2];
+  if (!(r2 > rho || (r2 == rho && id2 < id))) return;
+  const uint64_t key = (uint64_t(d2_of<D>(w.spts, x.ppos[e2], xq)) << kIdBits) | id2;
+  best = key < best ? key : best;
+}
+
+// Dense data (task-form plans): one wave per pick, then the wave's minimum.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sa_phase1(Plan p, Ws w, SaWs x) {
   __shared__ NearLds lds_all[kWavesPerBlock];
@@ -194,23 +208,33 @@ __global__ __launch_bounds__(kBlock) void k_sa_phase1(Plan p, Ws w, SaWs x) {
     const uint32_t e = uniform(x.ent[q]);
     const uint32_t rho = uniform(x.prho[e]), id = uniform(uint32_t(w.sid[q]));
     uint64_t best = kNoKey;
-    uint32_t last_e = e;  // consecutive positions often share a cell
-    wave_near<D>(p, w, xq, lds, [&](uint32_t j) {
-      const uint32_t e2 = x.ent[j];
-      if (e2 == e || e2 == last_e) return;
-      if (d2_of<D>(w.spts, j, xq) >= p.R) return;
-      last_e = e2;
-      const uint32_t r2 = x.prho[e2], id2 = x.pick[e2];
-      if (!(r2 > rho || (r2 == rho && id2 < id))) return;
-      const uint64_t key = (uint64_t(d2_of<D>(w.spts, x.ppos[e2], xq)) << kIdBits) | id2;
-      best = key < best ? key : best;
-    });
+    uint32_t last_e = e;
+    wave_near<D>(p, w, xq, lds, [&](uint32_t j) { sa_visit_d<D>(p, w, x, xq, e, rho, id, j, last_e, best); });
     best = wave_min_u64(best);
     if (lane_id() == 0) {
       w.best[q] = best;
       w.flag[q] = best == kNoKey ? 1 : 0;  // open for the second phase
     }
   }
+}
+
+// Sparse data (lane-form plans): one lane per pick.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_sa_phase1_lanes(Plan p, Ws w, SaWs x) {
+  if (grid_skipped(w.hdr)) return;
+  const uint32_t u = blockIdx.x * kBlock + threadIdx.x;
+  if (u >= x.cnt[0]) return;
+  const uint32_t q = x.plist[u];
+  int32_t xq[D];
+#pragma unroll
+  for (int t = 0; t < D; ++t) xq[t] = w.spts[int64_t(q) * D + t];
+  const uint32_t e = x.ent[q];
+  const uint32_t rho = x.prho[e], id = uint32_t(w.sid[q]);
+  uint64_t best = kNoKey;
+  uint32_t last_e = e;
+  lane_near<D>(p, w, xq, [&](uint32_t j) { sa_visit_d<D>(p, w, x, xq, e, rho, id, j, last_e, best); });
+  w.best[q] = best;
+  w.flag[q] = best == kNoKey ? 1 : 0;  // open for the second phase
 }
 
 // Outputs in id order: dep and the true distance from the key, the pick's density,
@@ -240,7 +264,10 @@ void launch_sa_d(const Plan &p, const Ws &w, const SApproxPlan &a, const SaWs &x
   DPC_LAUNCH((k_sa_insert<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, a, x);
   DPC_LAUNCH((k_sa_split), blocks_for(p.n, kBlock * kSplitPer), kBlock, s, p, w, x);
   DPC_LAUNCH((k_sa_keys), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
-  DPC_LAUNCH((k_sa_phase1<D>), persistent_blocks(p.n), kBlock, s, p, w, x);
+  if (p.lanes)
+    DPC_LAUNCH((k_sa_phase1_lanes<D>), blocks_for(p.n, kBlock), kBlock, s, p, w, x);
+  else
+    DPC_LAUNCH((k_sa_phase1<D>), persistent_blocks(p.n), kBlock, s, p, w, x);
 }
 
 }  // namespace
