@@ -236,7 +236,7 @@ def bench_serve(args, reqs) -> int:
     results = {}
     # continuous: `slots` streams for new jobs (small ones grouped) and one of its own for
     # re-thresholds; the comparison: one stream, every request in arrival order
-    for name, slots, group, relabel in (("continuous", args.slots, True, 1), ("one_slot_fifo", 1, False, 0)):
+    for name, slots, group, relabel in (("continuous", args.slots, True, 2), ("one_slot_fifo", 1, False, 0)):
         rq = [copy.copy(q) for q in reqs]
         srv = serve.Server(budget_bytes=64 << 30, slots=slots, group_small=group, relabel_slots=relabel)
         t0 = time.perf_counter()
@@ -272,7 +272,7 @@ def bench_serve(args, reqs) -> int:
         "config": {"workload": "serve", "duration_s": args.duration, "rate_per_s": 200.0,
                    "requests": len(reqs), "new": sum(1 for q in reqs if q.kind == "new"),
                    "rethreshold": sum(1 for q in reqs if q.kind == "rethreshold"), "slots": args.slots,
-                   "relabel_slots": 1, "hbm_budget_gb": 64},
+                   "relabel_slots": 2, "hbm_budget_gb": 64},
         "latency": main_r["latency"],
         "requests_per_s": main_r["requests_per_s"],
         "new_points_per_s": main_r["new_points_per_s"],
@@ -474,6 +474,7 @@ def main() -> int:
         "rooflines": res["rooflines"],
         "work": res["work"],
         "ncenters": res["ncenters"],
+        "decision_graph": res["decision_graph"],
     }
     approx, sapprox = {}, {}
     if not args.no_approx:
@@ -511,6 +512,40 @@ def _report(L) -> dict:
     buf = ctypes.create_string_buffer(8192)
     L.dpc_profile_report(buf, 8192)
     return json.loads(buf.value.decode())
+
+
+def bench_decision(job, out: dict, reps: int = 20) -> dict:
+    """Decision-graph summaries (Section 2.1) of one run's resident rho and delta: top-100
+    by delta, a 16 x 16 <rho, delta> histogram and the suggested delta_min, timed with
+    HIP events over `reps` repetitions each."""
+    import torch
+
+    from paper_2207_04649_amd import dpc
+
+    dev = out["rho"].device
+    ws = torch.empty(dpc.DECISION_WS_BYTES, dtype=torch.uint8, device=dev)
+    re = torch.logspace(0, 4, 17, dtype=torch.float64, device=dev)
+    de = torch.cat([torch.zeros(1, dtype=torch.float64, device=dev),
+                    torch.logspace(math.log10(job.d_cut / 8), math.log10(job.d_cut * 1e3), 15, dtype=torch.float64,
+                                   device=dev), torch.tensor([math.inf], dtype=torch.float64, device=dev)])
+    res = {}
+    for name, fn in (("top100_ms", lambda: dpc.dpc_decision_top(out["rho"], out["delta"], job.rho_min, 100, ws=ws)),
+                     ("histogram_16x16_ms", lambda: dpc.dpc_decision_histogram(out["rho"], out["delta"], re, de))):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        res[name] = a.elapsed_time(b) / reps
+        if name == "top100_ms":
+            top = r
+    dmin, cent = dpc.dpc_decision_suggest(top, job.d_cut)
+    res["suggested_delta_min"] = float(dmin.item())
+    res["suggested_centers"] = int(cent.item())
+    return res
 
 
 def bench_single(args, job, steps: int, warmup: int, with_roofline: bool) -> dict:
@@ -560,7 +595,7 @@ def bench_single(args, job, steps: int, warmup: int, with_roofline: bool) -> dic
             "kernels_ms_per_step": {k: v[1] / steps for k, v in prof.items() if k != "work" and v[0]},
             "roofline": dict(roofs[dom], kernel=dom), "rooflines": roofs,
             "work": dict(work, sum_rho=sum_rho), "ncenters": int(out["ncenters"].item()),
-            "label": out["label"]}
+            "label": out["label"], "decision_graph": bench_decision(job, out)}
 
 
 def bench_sapprox(job, steps: int, warmup: int, eps: float) -> dict:

@@ -18,6 +18,14 @@ first, when a new job needs their memory.  Requests that arrive while others
 are on the GPU are admitted as soon as a slot and memory free up, so their work
 overlaps on the device.  Latency is arrival -> labels in pinned host memory.
 
+Host staging.  Each slot owns two pinned host buffers, reused from request to
+request: coordinates are copied into one and sent to the device from there,
+labels (and, with keep_outputs, rho, dep and delta) come back into the other and
+are copied out to the request when its work has ended.  Pinned memory therefore
+stays bounded by the slots and the largest group, whatever the length of the
+trace (pinning memory per request grows with the trace, and pinning tens of GB
+can stall in the driver).
+
 Every result equals that of the job run alone: the kernels are deterministic
 and jobs share no device memory.
 """
@@ -51,9 +59,9 @@ class Req:
     job_key: int = -1           # the job the request created or re-thresholded
     t_done: float = -1.0
     dropped: bool = False       # re-threshold with no job ready (nothing to re-threshold)
-    labels: torch.Tensor | None = None    # pinned host copies
+    labels: torch.Tensor | None = None    # host copies (through the slot's pinned staging)
     ncenters: torch.Tensor | None = None
-    rho: torch.Tensor | None = None       # new jobs, with keep_outputs: pinned host copies
+    rho: torch.Tensor | None = None       # new jobs, with keep_outputs: host copies
     dep: torch.Tensor | None = None
     delta: torch.Tensor | None = None
 
@@ -86,6 +94,7 @@ class Inflight:
     keep: list                  # tensors and host buffers that must live until the work ends
     new: bool
     batch: object = None        # dpc_batch handle to free
+    outs: list = dataclasses.field(default_factory=list)  # (request, field, staged host view)
 
 
 class Server:
@@ -109,6 +118,8 @@ class Server:
         self.next_key = 0
         self.label_ws = [torch.empty(dpc.DPC_LABEL_WS_BYTES, dtype=torch.uint8, device=self.dev)
                          for _ in range(len(self.streams))]
+        self.stage_in: list = [None] * len(self.streams)   # pinned host staging per slot
+        self.stage_out: list = [None] * len(self.streams)
         self.stats = collections.Counter()
         self.peak_used = 0
         self.new_outstanding = 0  # new-job requests of the run not yet admitted
@@ -130,16 +141,54 @@ class Server:
             self.stats["evicted"] += 1
         return self.used + need <= self.budget
 
+    # ---- host staging ----
+    @staticmethod
+    def _stage(bufs: list, slot: int, nbytes: int) -> torch.Tensor:
+        """The slot's pinned buffer of at least nbytes (grown at least twofold, never
+        shrunk, so a slot allocates a few times at most; the slot's previous work has
+        ended, so the old buffer is free)."""
+        old = bufs[slot]
+        if old is None or old.numel() < nbytes:
+            grow = 2 * old.numel() if old is not None else 0
+            bufs[slot] = torch.empty(max(nbytes, grow, 1 << 20), dtype=torch.uint8, pin_memory=True)
+        return bufs[slot]
+
+    @staticmethod
+    def _carve(stage: torch.Tensor, at: int, count: int, dtype: torch.dtype) -> tuple[torch.Tensor, int]:
+        """A view of `count` items of dtype at byte offset `at` (256-aligned); the next offset."""
+        size = torch.empty(0, dtype=dtype).element_size() * count
+        view = stage[at: at + size].view(dtype)
+        return view, at + (size + 255) // 256 * 256
+
+    def _out_views(self, reqs: list[Req], ns: list[int], slot: int, full: bool) -> list:
+        """Staged host views of each request's outputs: [(req, {field: view})]."""
+        per = [4 * n + 8 + (16 * n if full else 0) + 5 * 256 for n in ns]
+        stage = self._stage(self.stage_out, slot, sum(per))
+        at, views = 0, []
+        for q, n in zip(reqs, ns):
+            v = {}
+            v["labels"], at = self._carve(stage, at, n, torch.int32)
+            v["ncenters"], at = self._carve(stage, at, 1, torch.int64)
+            if full:
+                v["rho"], at = self._carve(stage, at, n, torch.int32)
+                v["dep"], at = self._carve(stage, at, n, torch.int32)
+                v["delta"], at = self._carve(stage, at, n, torch.float64)
+            views.append((q, v))
+        return views
+
     # ---- launching ----
     def _launch_new(self, reqs: list[Req], slot: int, now: float, ws_bytes: int) -> None:
         stream = self.streams[slot]
         jobs, keep = [], []
         batch = None
+        stage = self._stage(self.stage_in, slot, sum(q.pts.nbytes + 256 for q in reqs))
+        at = 0
         with torch.cuda.stream(stream):
             for q in reqs:
                 n, d = q.pts.shape
-                host = torch.from_numpy(q.pts).pin_memory()
-                keep.append(host)
+                host, at = self._carve(stage, at, n * d, torch.int32)
+                host.numpy()[:] = q.pts.reshape(-1)
+                host = host.view(n, d)
                 pts = host.to(self.dev, non_blocking=True)
                 dev = lambda dt: torch.empty(n, dtype=dt, device=self.dev)  # noqa: E731
                 r = Resident(q.job_key, n, d, q.d_cut, pts, dev(torch.int32), dev(torch.int32), dev(torch.float64),
@@ -160,23 +209,19 @@ class Server:
                 assert nbytes <= ws_bytes
                 dpc.dpc_batch_bind(batch, ws)
                 dpc.dpc_batch_run(batch, ws, stream=stream)
-            for q, r in zip(reqs, jobs):
-                q.labels = torch.empty(r.n, dtype=torch.int32, pin_memory=True)
-                q.ncenters = torch.empty(1, dtype=torch.int64, pin_memory=True)
-                q.labels.copy_(r.label, non_blocking=True)
-                q.ncenters.copy_(r.ncenters, non_blocking=True)
+            outs = self._out_views(reqs, [r.n for r in jobs], slot, self.keep_outputs)
+            for (q, v), r in zip(outs, jobs):
+                v["labels"].copy_(r.label, non_blocking=True)
+                v["ncenters"].copy_(r.ncenters, non_blocking=True)
                 if self.keep_outputs:
-                    q.rho = torch.empty(r.n, dtype=torch.int32, pin_memory=True)
-                    q.dep = torch.empty(r.n, dtype=torch.int32, pin_memory=True)
-                    q.delta = torch.empty(r.n, dtype=torch.float64, pin_memory=True)
-                    q.rho.copy_(r.rho, non_blocking=True)
-                    q.dep.copy_(r.dep, non_blocking=True)
-                    q.delta.copy_(r.delta, non_blocking=True)
+                    v["rho"].copy_(r.rho, non_blocking=True)
+                    v["dep"].copy_(r.dep, non_blocking=True)
+                    v["delta"].copy_(r.delta, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
         for r in jobs:
             self.resident[r.key] = r
-        self.inflight.append(Inflight(ev, slot, reqs, jobs, ws_bytes, keep, True, batch))
+        self.inflight.append(Inflight(ev, slot, reqs, jobs, ws_bytes, keep, True, batch, outs))
         self.stats["new_launches"] += 1
         self.stats["new_jobs"] += len(reqs)
 
@@ -190,13 +235,12 @@ class Server:
             nc = torch.empty(1, dtype=torch.int64, device=self.dev)
             dpc.dpc_label(r.rho, r.dep, r.delta, q.rho_min, q.delta_min, label=lab, ncenters=nc,
                           ws=self.label_ws[slot], stream=stream)
-            q.labels = torch.empty(r.n, dtype=torch.int32, pin_memory=True)
-            q.ncenters = torch.empty(1, dtype=torch.int64, pin_memory=True)
-            q.labels.copy_(lab, non_blocking=True)
-            q.ncenters.copy_(nc, non_blocking=True)
+            outs = self._out_views([q], [r.n], slot, False)
+            outs[0][1]["labels"].copy_(lab, non_blocking=True)
+            outs[0][1]["ncenters"].copy_(nc, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
-        self.inflight.append(Inflight(ev, slot, [q], [r], 0, [lab, nc], False))
+        self.inflight.append(Inflight(ev, slot, [q], [r], 0, [lab, nc], False, None, outs))
         self.stats["relabels"] += 1
 
     def _retire(self, now: float) -> int:
@@ -207,6 +251,9 @@ class Server:
                 continue
             for q in f.reqs:
                 q.t_done = now
+            for q, v in f.outs:  # out of the slot's staging buffer before the slot is reused
+                for field, view in v.items():
+                    setattr(q, field, view.clone())
             for r in f.jobs:
                 r.busy -= 1
                 if f.new:
@@ -236,8 +283,11 @@ class Server:
         if q.kind == "rethreshold":
             ready = [k for k, r in self.resident.items() if r.ready]
             if not ready:
-                if self.new_outstanding or any(not r.ready for r in self.resident.values()):
-                    return False  # a job is being computed or will be: wait for it
+                # Wait for a job being computed, or (with a queue of its own) for one
+                # still to come.  With one queue for everything a job still to come is
+                # behind this request, so waiting for it would stall the queue for good.
+                if any(not r.ready for r in self.resident.values()) or (self.new_outstanding and not self.shared):
+                    return False
                 queue.popleft()
                 q.dropped = True
                 q.t_done = now
@@ -274,14 +324,22 @@ class Server:
         self._launch_new(group, self.free_slots.pop(0), now, ws_bytes)
         return True
 
-    def run(self, requests: list[Req], clock=time.perf_counter) -> list[Req]:
-        """Replay `requests` in real time (by t_arrival); returns them with t_done set."""
+    def run(self, requests: list[Req], clock=time.perf_counter, progress=None) -> list[Req]:
+        """Replay `requests` in real time (by t_arrival); returns them with t_done set.
+        ``progress(finished, total)`` is called each time another 1000 requests have
+        finished, and at least every 20 s."""
         pending = collections.deque(sorted(requests, key=lambda q: q.t_arrival))
         queues = {"new": collections.deque(), "rethreshold": collections.deque()}
         self.new_outstanding = sum(1 for q in requests if q.kind == "new")
         finished = 0
+        reported = 0
         t0 = clock()
+        t_report = t0
         while finished < len(requests):
+            if progress is not None and (finished >= reported + 1000 or clock() - t_report >= 20.0):
+                reported = max(reported, finished - finished % 1000)
+                t_report = clock()
+                progress(finished, len(requests))
             now = clock() - t0
             while pending and pending[0].t_arrival <= now:
                 q = pending.popleft()
@@ -291,7 +349,11 @@ class Server:
             for kind in ("rethreshold", "new"):
                 queue = queues[kind]
                 free = self.free_relabel if (kind == "rethreshold" and not self.shared) else self.free_slots
-                while queue and free:
+                # every waiting re-threshold a slot allows, but one new launch per pass:
+                # a launch's host work (staging, planning) must not hold re-thresholds back
+                budget = len(queue) if kind == "rethreshold" else 1
+                while queue and free and budget > 0:
+                    budget -= 1
                     dropped = self.stats["dropped"]
                     if not self._admit(queue, now):
                         if not self.inflight and queue[0].kind == "new":
