@@ -129,12 +129,15 @@ GROUP_KERNELS = {
     "finish": ("k_finish",),
     "label": ("k_label_init", "k_jump", "k_root"),
 }
-# walks_4m_d4: the counters of profiles/hbm_counters_walks_4m_d4.txt (groups whose
-# kernels run only in them; k_jump runs 3 times per step).
+# The counters of profiles/hbm_counters_<workload>.txt (groups whose kernels run
+# only in them; k_jump runs 3 times per step).
 HBM_BYTES: dict = {  # {workload: {"source": hash, group: bytes per launch}}
-    "walks_4m_d4": {"source": "b53d3edb1ee348d3", "ringk": 4757.3e6, "search": (1057.6 + 5.0) * 1e6,
-                    "density": 890.4e6, "finish": 1044.1e6, "peaks": (45.9 + 42.6) * 1e6,
+    "walks_4m_d4": {"source": "609bf7a7ba72f254", "ringk": 4757.5e6, "search": (1058.3 + 5.0) * 1e6,
+                    "density": 889.7e6, "finish": 1044.2e6, "peaks": (45.2 + 42.7) * 1e6,
                     "label": (40.8 + 3 * 18.4 + 17.8) * 1e6},
+    "blobs_1m_d2": {"source": "609bf7a7ba72f254", "ringk": 121.5e6, "search": (128.2 + 1.4) * 1e6,
+                    "density": 67.5e6, "finish": 194.6e6, "peaks": (43.8 + 93.5) * 1e6,
+                    "label": (53.0 + 3 * 40.5 + 39.1) * 1e6},
 }
 
 
