@@ -39,10 +39,11 @@ def check(got, pts, d_cut, rho_min, delta_min, ctx=""):
 
 
 # Cut-offs keep the exact grid's dense cell table small enough to emulate.
+# (the larger sizes on the first seed only: the suite stays within minutes)
 CASES = [(seed, d, n, dc) for seed in range(2)
          for d, dc, ns in [(1, 40.0, (3, 700)), (2, 300.0, (1, 200, 700)), (2, 3000.0, (200,)),
                            (3, 2000.0, (200,)), (4, 4500.0, (150,)), (6, 14000.0, (40,)), (8, 27000.0, (12,))]
-         for n in ns]
+         for n in ns if seed == 0 or n < 500]
 
 
 @pytest.mark.parametrize("seed,d,n,d_cut", CASES)
