@@ -482,7 +482,7 @@ def main() -> int:
     approx, sapprox = {}, {}
     if not args.no_approx:
         approx[job.name] = bench_approx(job, max(3, args.steps // 2), 2, res["label"])
-        sapprox[job.name] = bench_sapprox(job, max(3, args.steps // 2), 2, args.eps)
+        sapprox[job.name] = bench_sapprox(job, max(3, args.steps // 2), 2, args.eps, res["label"])
     if args.extra and args.extra != job.name:
         ex = inputs.WORKLOADS[args.extra]()
         r2 = bench_single(args, ex, max(3, args.steps // 2), 2, with_roofline=True)
@@ -491,7 +491,12 @@ def main() -> int:
                                    "roofline": r2["roofline"]}}
         if not args.no_approx:
             approx[ex.name] = bench_approx(ex, max(3, args.steps // 2), 2, r2["label"])
-            sapprox[ex.name] = bench_sapprox(ex, max(3, args.steps // 2), 2, args.eps)
+            sapprox[ex.name] = bench_sapprox(ex, max(3, args.steps // 2), 2, args.eps, r2["label"])
+            # the time / accuracy trade-off over eps (the shape of Table 5)
+            sapprox[ex.name]["eps_sweep"] = {
+                str(e): {k: r[k] for k in ("ms_per_step", "picked_fraction", "rand_index_vs_exact")}
+                for e in (0.25, 0.5, 1.0)
+                for r in [bench_sapprox(ex, max(3, args.steps // 2), 1, e, r2["label"])]}
     if approx:
         line["approx_dpc"] = approx
         line["s_approx_dpc"] = sapprox
@@ -601,8 +606,27 @@ def bench_single(args, job, steps: int, warmup: int, with_roofline: bool) -> dic
             "label": out["label"], "decision_graph": bench_decision(job, out)}
 
 
-def bench_sapprox(job, steps: int, warmup: int, eps: float) -> dict:
-    """Time `steps` dpc_sapprox_run calls (S-Approx-DPC, Section 5) on resident input."""
+def rand_index(a, b) -> float:
+    """Rand index of two device labelings (noise, -1, counts as one more cluster): the
+    fraction of point pairs on which they agree, from the contingency counts."""
+    import torch
+
+    ia = torch.unique(a, return_inverse=True)[1].to(torch.int64)
+    ib = torch.unique(b, return_inverse=True)[1].to(torch.int64)
+    pair = torch.unique(ia * (int(ib.max().item()) + 1) + ib, return_counts=True)[1]
+
+    def c2(x):
+        x = x.to(torch.int64)
+        return int((x * (x - 1) // 2).sum().item())
+
+    n = a.numel()
+    tot = n * (n - 1) // 2
+    return (tot + 2 * c2(pair) - c2(torch.bincount(ia)) - c2(torch.bincount(ib))) / tot
+
+
+def bench_sapprox(job, steps: int, warmup: int, eps: float, exact_label=None) -> dict:
+    """Time `steps` dpc_sapprox_run calls (S-Approx-DPC, Section 5) on resident input; with
+    the exact labels, also their Rand index against S-Approx-DPC's."""
     import torch
 
     from paper_2207_04649_amd import dpc
@@ -631,7 +655,8 @@ def bench_sapprox(job, steps: int, warmup: int, eps: float) -> dict:
             "ms_per_step": (t1 - t0) * 1000.0 / steps,
             "kernels_ms_per_step": {k: v[1] / steps for k, v in prof.items() if k != "work" and v[0]},
             "picked_fraction": float(out["picked"].float().mean().item()),
-            "ncenters": int(out["ncenters"].item())}
+            "ncenters": int(out["ncenters"].item()),
+            "rand_index_vs_exact": None if exact_label is None else rand_index(out["label"], exact_label)}
 
 
 def bench_approx(job, steps: int, warmup: int, exact_label) -> dict:
@@ -670,7 +695,8 @@ def bench_approx(job, steps: int, warmup: int, exact_label) -> dict:
     return {"value": job.n * steps / (t1 - t0), "unit": "points/s", "ms_per_step": (t1 - t0) * 1000.0 / steps,
             "kernels_ms_per_step": {k: v[1] / steps for k, v in prof.items() if k != "work" and v[0]},
             "approximate_fraction": float(out["approx"].float().mean().item()),
-            "centers_and_noise_equal_exact": same}
+            "centers_and_noise_equal_exact": same,
+            "rand_index_vs_exact": None if exact_label is None else rand_index(out["label"], exact_label)}
 
 
 if __name__ == "__main__":

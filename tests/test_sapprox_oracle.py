@@ -122,3 +122,35 @@ def test_mutant_caught(monkeypatch, name):
     attr, make = MUTANTS[name]
     monkeypatch.setattr(S, attr, make(getattr(S, attr)))
     assert _all_pins(), name
+
+
+def _rand_index(a, b):
+    """Rand index of two labelings (noise, -1, counts as one more cluster)."""
+    _, ia = np.unique(np.asarray(a), return_inverse=True)
+    _, ib = np.unique(np.asarray(b), return_inverse=True)
+    m = np.zeros((ia.max() + 1, ib.max() + 1), np.int64)
+    np.add.at(m, (ia.reshape(-1), ib.reshape(-1)), 1)
+    c2 = lambda x: int((x * (x - 1) // 2).sum())  # noqa: E731
+    n = ia.size
+    tot = n * (n - 1) // 2
+    return (tot + 2 * c2(m) - c2(m.sum(1)) - c2(m.sum(0))) / tot
+
+
+def test_rand_index_falls_as_eps_grows():
+    # The trend of Table 5 (weak: the section claims no guarantee), on two seeded
+    # blob jobs: the Rand index against the exact labels does not rise with eps,
+    # and fewer points are picked.  Approx-DPC keeps the exact clustering here.
+    from oracle import approx_oracle
+    for seed in (61, 62):
+        job = inputs.blob_job(seed, 3000, 2, 6, 500.0, 2500.0, 0.05)
+        ex = dpc_oracle.dpc(job.pts, job.d_cut, job.rho_min, job.delta_min)
+        ax = approx_oracle.approx_dpc(job.pts, job.d_cut, job.rho_min, job.delta_min)
+        assert _rand_index(ex["label"], ax["label"]) >= 0.999
+        ri, picks = [], []
+        for eps in (0.1, 0.4, 0.7, 1.0):
+            sx = S.sapprox_dpc(job.pts, job.d_cut, eps, job.rho_min, job.delta_min)
+            ri.append(_rand_index(ex["label"], sx["label"]))
+            picks.append(int(sx["picked"].sum()))
+        assert all(a >= b for a, b in zip(ri, ri[1:])), ri
+        assert all(a > b for a, b in zip(picks, picks[1:])), picks
+        assert ri[-1] > 0.95
