@@ -79,30 +79,44 @@ __global__ __launch_bounds__(kBlock) void k_ax_clear(AxWs x, uint32_t slots) {
 // and lowers its smallest density.  Slots only ever go from free to taken, so a
 // stale free slot read is settled by the compare-and-swap, and a taken one is
 // final.  The table has more slots than points, so a free slot always exists.
+// Consecutive lanes of one cell (cell order keeps a cell's points together)
+// combine their keys first, and the last of them updates the slot: one pair of
+// atomics per run instead of per point.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_ax_insert(Plan p, Ws w, ApproxPlan a, AxWs x) {
+  if (grid_skipped(w.hdr)) return;
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (q >= p.n || grid_skipped(w.hdr)) return;
-  int32_t c[D];
+  const bool valid = q < p.n;
+  uint32_t h = kEmpty;  // (no slot has this index)
+  uint64_t K = 0;
+  if (valid) {
+    int32_t c[D];
 #pragma unroll
-  for (int t = 0; t < D; ++t) c[t] = w.spts[q * D + t] / a.La;
-  uint32_t h = cell_hash<D>(c) & a.mask;
-  for (uint32_t probe = 0; probe <= a.mask; ++probe) {
-    uint32_t r = x.rep[h];
-    if (r == kEmpty) {
-      r = atomicCAS(&x.rep[h], kEmpty, uint32_t(q));
-      if (r == kEmpty) break;  // opened by this point
+    for (int t = 0; t < D; ++t) c[t] = w.spts[q * D + t] / a.La;
+    h = cell_hash<D>(c) & a.mask;
+    for (uint32_t probe = 0; probe <= a.mask; ++probe) {
+      uint32_t r = x.rep[h];
+      if (r == kEmpty) {
+        r = atomicCAS(&x.rep[h], kEmpty, uint32_t(q));
+        if (r == kEmpty) break;  // opened by this point
+      }
+      bool same = true;
+#pragma unroll
+      for (int t = 0; t < D; ++t) same = same && w.spts[int64_t(r) * D + t] / a.La == c[t];
+      if (same) break;
+      h = (h + 1) & a.mask;
     }
-    bool same = true;
-#pragma unroll
-    for (int t = 0; t < D; ++t) same = same && w.spts[int64_t(r) * D + t] / a.La == c[t];
-    if (same) break;
-    h = (h + 1) & a.mask;
+    K = w.sK[q];
+    x.ent[q] = h;
   }
-  const uint64_t K = w.sK[q];
-  x.ent[q] = h;
-  atomicMax(reinterpret_cast<unsigned long long *>(&x.top[h]), static_cast<unsigned long long>(K));
-  atomicMin(&x.minrho[h], uint32_t(K >> 32));
+  const WaveRun run = wave_run(h);
+  const uint64_t top = run_reduce(K, run.start, [](uint64_t u, uint64_t v) { return u > v ? u : v; });
+  const uint32_t low = run_reduce(valid ? uint32_t(K >> 32) : kEmpty, run.start,
+                                  [](uint32_t u, uint32_t v) { return u < v ? u : v; });
+  if (valid && run.tail) {
+    atomicMax(reinterpret_cast<unsigned long long *>(&x.top[h]), static_cast<unsigned long long>(top));
+    atomicMin(&x.minrho[h], low);
+  }
 }
 
 // First rule: a point other than its cell's p* takes p*(c).  The p* points are

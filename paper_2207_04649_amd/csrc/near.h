@@ -6,6 +6,39 @@
 
 namespace dpc {
 
+// Runs of equal keys among consecutive lanes (points in cell order often share a
+// cell of a coarser grid): the first lane of the calling lane's run, and whether
+// the calling lane ends its run.  Every lane of the wave calls it.
+struct WaveRun {
+  int start;
+  bool tail;
+};
+
+__device__ __forceinline__ WaveRun wave_run(uint32_t key) {
+  const int lane = lane_id();
+  const uint32_t prev = __shfl_up(key, 1, kWave), next = __shfl(key, (lane + 1) & (kWave - 1), kWave);
+  int start = (lane == 0 || prev != key) ? lane : 0;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int o = __shfl_up(start, off, kWave);
+    if (lane >= off) start = max(start, o);
+  }
+  return WaveRun{start, lane == kWave - 1 || next != key};
+}
+
+// The combination by `op` of v over the lanes start .. lane of the calling lane's
+// run (inclusive); at the run's tail, over the whole run.  Every lane calls it.
+template <class T, class Op>
+__device__ __forceinline__ T run_reduce(T v, int start, Op op) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const T o = __shfl_up(v, off, kWave);
+    if (lane - off >= start) v = op(v, o);
+  }
+  return v;
+}
+
 // Calls f(j) on the calling lane for every cell-order position j of the exact
 // grid's rows that can hold a point within d_cut of xq (the lane's own query):
 // the same box as wave_near, row by row with an odometer.  For sparse data, where

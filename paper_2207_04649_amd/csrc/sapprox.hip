@@ -84,29 +84,38 @@ __global__ __launch_bounds__(kBlock) void k_sa_clear(SaWs x, uint32_t slots) {
   }
 }
 
-// Each point finds (or opens) its cell's slot and lowers the slot's pick id.
+// Each point finds (or opens) its cell's slot and lowers the slot's pick id;
+// consecutive lanes of one cell combine first (one atomic per run).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sa_insert(Plan p, Ws w, SApproxPlan a, SaWs x) {
+  if (grid_skipped(w.hdr)) return;
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (q >= p.n || grid_skipped(w.hdr)) return;
-  int32_t c[D];
+  const bool valid = q < p.n;
+  uint32_t h = kEmpty;  // (no slot has this index)
+  uint32_t id = kEmpty;
+  if (valid) {
+    int32_t c[D];
 #pragma unroll
-  for (int t = 0; t < D; ++t) c[t] = w.spts[q * D + t] / a.Le;
-  uint32_t h = cell_hash<D>(c) & a.mask;
-  for (uint32_t probe = 0; probe <= a.mask; ++probe) {
-    uint32_t r = x.rep[h];
-    if (r == kEmpty) {
-      r = atomicCAS(&x.rep[h], kEmpty, uint32_t(q));
-      if (r == kEmpty) break;
+    for (int t = 0; t < D; ++t) c[t] = w.spts[q * D + t] / a.Le;
+    h = cell_hash<D>(c) & a.mask;
+    for (uint32_t probe = 0; probe <= a.mask; ++probe) {
+      uint32_t r = x.rep[h];
+      if (r == kEmpty) {
+        r = atomicCAS(&x.rep[h], kEmpty, uint32_t(q));
+        if (r == kEmpty) break;
+      }
+      bool same = true;
+#pragma unroll
+      for (int t = 0; t < D; ++t) same = same && w.spts[int64_t(r) * D + t] / a.Le == c[t];
+      if (same) break;
+      h = (h + 1) & a.mask;
     }
-    bool same = true;
-#pragma unroll
-    for (int t = 0; t < D; ++t) same = same && w.spts[int64_t(r) * D + t] / a.Le == c[t];
-    if (same) break;
-    h = (h + 1) & a.mask;
+    x.ent[q] = h;
+    id = uint32_t(w.sid[q]);
   }
-  x.ent[q] = h;
-  atomicMin(&x.pick[h], uint32_t(w.sid[q]));
+  const WaveRun run = wave_run(h);
+  const uint32_t low = run_reduce(id, run.start, [](uint32_t u, uint32_t v) { return u < v ? u : v; });
+  if (valid && run.tail) atomicMin(&x.pick[h], low);
 }
 
 // The picks: their positions and densities per slot, and as a list
