@@ -239,7 +239,7 @@ def bench_serve(args, reqs) -> int:
     results = {}
     # continuous: `slots` streams for new jobs (small ones grouped) and one of its own for
     # re-thresholds; the comparison: one stream, every request in arrival order
-    for name, slots, group, relabel in (("continuous", args.slots, True, 2), ("one_slot_fifo", 1, False, 0)):
+    for name, slots, group, relabel in (("continuous", args.slots, True, 8), ("one_slot_fifo", 1, False, 0)):
         rq = [copy.copy(q) for q in reqs]
         srv = serve.Server(budget_bytes=64 << 30, slots=slots, group_small=group, relabel_slots=relabel)
         t0 = time.perf_counter()
@@ -275,7 +275,7 @@ def bench_serve(args, reqs) -> int:
         "config": {"workload": "serve", "duration_s": args.duration, "rate_per_s": 200.0,
                    "requests": len(reqs), "new": sum(1 for q in reqs if q.kind == "new"),
                    "rethreshold": sum(1 for q in reqs if q.kind == "rethreshold"), "slots": args.slots,
-                   "relabel_slots": 2, "hbm_budget_gb": 64},
+                   "relabel_slots": 8, "hbm_budget_gb": 64},
         "latency": main_r["latency"],
         "requests_per_s": main_r["requests_per_s"],
         "new_points_per_s": main_r["new_points_per_s"],
