@@ -182,3 +182,50 @@ def test_approx_workspace_bytes():
     assert lib.dpc_approx_workspace_bytes(0, 2, 3.0) == 0
     assert lib.dpc_approx_workspace_bytes(10, 9, 3.0) == 0
     assert lib.dpc_approx_workspace_bytes(10, 2, -1.0) == 0
+
+
+def test_approximate_and_decision_entries_reject_before_any_device_call():
+    """The Approx-DPC, S-Approx-DPC and decision-graph calls check their arguments
+    and workspace sizes on the host, before any HIP call."""
+    L = dpc.lib()
+    P = ctypes.c_void_p
+    fake = P(4096)
+    n, d, dc = 10, 2, 3.0
+    exact = dpc.dpc_workspace_bytes(n, d, dc)
+    ax = L.dpc_approx_workspace_bytes(n, d, dc)
+    sx = L.dpc_sapprox_workspace_bytes(n, d, dc, 0.5)
+    assert ax > exact and sx > exact
+
+    def approx(pts=fake, n=n, rho_min=1, delta_min=4.0, out=fake, ws_bytes=ax):
+        return L.dpc_approx_run(pts, n, d, dc, rho_min, delta_min, out, out, out, out, out, P(0), fake, ws_bytes,
+                                P(0))
+    assert approx(pts=P(0)) == dpc.DPC_EINVAL
+    assert approx(n=0) == dpc.DPC_EINVAL
+    assert approx(rho_min=-1) == dpc.DPC_EINVAL
+    assert approx(delta_min=dc) == dpc.DPC_EINVAL            # Theorem 4 needs delta_min > d_cut
+    assert approx(out=P(0)) == dpc.DPC_EINVAL
+    assert approx(ws_bytes=exact) == dpc.DPC_EWORKSPACE      # the exact path's workspace is too small
+    assert b"dpc_approx_workspace_bytes" in L.dpc_last_error()
+
+    def sapprox(eps=0.5, delta_min=4.0, ws_bytes=sx):
+        return L.dpc_sapprox_run(fake, n, d, dc, eps, 1, delta_min, fake, fake, fake, fake, fake, P(0), fake,
+                                 ws_bytes, P(0))
+    for bad in (0.0, -1.0, 1.5, float("nan"), float("inf")):
+        assert sapprox(eps=bad, ws_bytes=exact) == dpc.DPC_EINVAL
+        assert L.dpc_sapprox_workspace_bytes(n, d, dc, bad) == 0
+    assert sapprox(delta_min=2.0) == dpc.DPC_EINVAL
+    assert sapprox(ws_bytes=exact) == dpc.DPC_EWORKSPACE
+
+    ws = dpc.DECISION_WS_BYTES
+    top = lambda k, nn=n, b=ws, ptr=fake: L.dpc_decision_top(nn, ptr, fake, 1, k, fake, fake, P(0), fake, fake, b,  # noqa: E731
+                                                             P(0))
+    assert top(0) == dpc.DPC_EINVAL and top(dpc.DECISION_TOP_MAX + 1) == dpc.DPC_EINVAL
+    assert top(5, nn=0) == dpc.DPC_EINVAL and top(5, ptr=P(0)) == dpc.DPC_EINVAL
+    assert top(5, b=ws - 1) == dpc.DPC_EWORKSPACE
+    hist = lambda nr, nd, nn=n: L.dpc_decision_histogram(nn, fake, fake, fake, nr, fake, nd, fake, P(0))  # noqa: E731
+    assert hist(0, 4) == dpc.DPC_EINVAL and hist(4, 0) == dpc.DPC_EINVAL
+    assert hist(1 << 13, (1 << 11) + 1) == dpc.DPC_EINVAL    # more than 2^24 bins
+    assert hist(4, 4, nn=0) == dpc.DPC_EINVAL
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.dpc_decision_suggest(fake, fake, bad, fake, fake, P(0)) == dpc.DPC_EINVAL
+    assert L.dpc_decision_suggest(P(0), fake, 1.0, fake, fake, P(0)) == dpc.DPC_EINVAL
