@@ -2,9 +2,10 @@
 // eps * d_cut / sqrt(d) stands for its cell.
 //
 //   * G' is an open-addressing hash table over the occupied cells (as in
-//     Approx-DPC); integer side Le = 1 + floor(sqrt((Re - 1) / d)), Re =
-//     ceil((eps d_cut)^2), so the points of a cell lie strictly within eps * d_cut
-//     of each other.  A cell's pick is its smallest id (one atomicMin per point).
+//     Approx-DPC); integer side Le = 1 + floor(sqrt((Re - 1) / d)), Re = ceil(e^2)
+//     for the double e = eps * d_cut, so the points of a cell lie strictly within e
+//     of each other.  A cell's pick is its smallest id (an atomicMin per run of
+//     same-cell lanes).
 //   * Local density of the picks (Def. 1, against all points).  The section
 //     computes it for the picks only; here the exact path's density kernels run
 //     over every point, which on this hardware costs less than a range search
