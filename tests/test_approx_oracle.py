@@ -41,6 +41,9 @@ def _cases():
     out.append((job.pts, job.d_cut))
     job = inputs.blob_job(32, 300, 3, 3, 300.0, 900.0, 0.1)
     out.append((job.pts, job.d_cut))
+    out.append((inputs.uniform_points(200, 3, 6, 33), 1.5))     # R = 3 <= d: cells of side 1
+    out.append((inputs.uniform_points(80, 8, 40, 34), 60.0))    # d = 8
+    out.append((np.repeat(inputs.uniform_points(30, 2, 20, 35), 3, axis=0), 5.0))  # duplicates
     return out
 
 
